@@ -1,0 +1,225 @@
+"""Benchmark of the per-pixel GBP hot path on one MI355X.
+
+A step tracks one 640x480 frame of the seeded piecewise-planar sequence
+(12 planes, inverse depths U[0.2, 2.0], pixel noise 0.02, 10% occluders):
+frame preparation, 20 synchronous GBP iterations (fused schedule), pose and
+statistics reductions and the inverse-depth/variance maps, re-anchoring when
+the keyframe test fires. Frames are staged in device memory before timing.
+
+Prints one JSON line: throughput in Mpixel-iter/s, the roofline of the
+dominant kernel (the fused iteration pass, timed with HIP events on the
+library stream), the FP64 CPU oracle timed on a bounded sample of the same
+workload, and the per-factor schedule measured on the same GPU.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+# algorithmic bytes per pixel-iteration of one fused pass: the 123 FP32 state
+# values read and written once, the keyframe intensity and two normal targets,
+# and one read of the warped target intensity and its two gradients
+STATE_PLANES = 123
+BYTES_PER_PX_ITER = STATE_PLANES * 4 * 2 + 4 + 8 + 12
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fused_iterate_vga.json")
+KERNEL_SOURCES = ["paper_2606_03989_amd/csrc/gbp_kernels.hip", "paper_2606_03989_amd/csrc/gbp_device.hpp"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def vga_inputs(n_frames: int):
+    import numpy as np
+    from synth.scenes import SEQUENCE_CONFIGS, make_sequence_scene, render_sequence_frame, sequence_poses
+    cfg = SEQUENCE_CONFIGS["vga"]
+    scene, cam = make_sequence_scene(cfg)
+    poses = sequence_poses(cfg)
+    I0, _, N0, _ = render_sequence_frame(cfg, scene, cam, poses, 0, keyframe=True)
+    frames, normals = [], []
+    for f in range(1, n_frames + 1):
+        img, _, nrm, _ = render_sequence_frame(cfg, scene, cam, poses, f % cfg.n_frames)
+        frames.append(img)
+        normals.append(np.ascontiguousarray(nrm))
+    return cam, I0, np.ascontiguousarray(N0), frames, normals
+
+
+VGA_PARAMS = dict(sigma_P=0.01, huber_k=10.0)
+
+
+def run_gpu(args):
+    import numpy as np
+    import torch
+    import paper_2606_03989_amd as pv
+
+    n_frames = args.warmup + args.steps
+    log(f"rendering {n_frames} frames of the 640x480 sequence")
+    cam, I0, N0, frames, normals = vga_inputs(n_frames)
+    H, W = cam.H, cam.W
+    dev = torch.device("cuda:0")
+    d_I0 = torch.from_numpy(I0).to(dev)
+    d_N0 = torch.from_numpy(N0).to(dev)
+    d_frames = [torch.from_numpy(f).to(dev) for f in frames]
+    d_normals = [torch.from_numpy(n).to(dev) for n in normals]
+    stream = torch.cuda.current_stream()
+
+    def make(schedule):
+        t = pv.Tracker(H, W, (cam.fx, cam.fy, cam.cx, cam.cy), **VGA_PARAMS)
+        t.set_stream(stream)
+        t.set_schedule(schedule)
+        t.set_keyframe(d_I0, d_N0)
+        return t
+
+    def step(t, i, iters):
+        r = t.track(d_frames[i], iters, maps=True, out_device=True)
+        if r["flags"] & pv.KEYFRAME_DUE:
+            t.set_keyframe(d_frames[i], d_normals[i])
+        return r
+
+    iters = args.iters
+    t = make(pv.SCHED_FUSED)
+    for i in range(args.warmup):
+        step(t, i, iters)
+    torch.cuda.synchronize()
+    t.profile(True)
+    for k in range(4):
+        t.profile_read(k)
+    t0 = time.perf_counter()
+    flags = 0
+    for i in range(args.warmup, args.warmup + args.steps):
+        r = step(t, i, iters)
+        flags |= r["flags"]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    it_ms, it_n = t.profile_read(pv.PROF_FUSED_ITERATE)
+    fin_ms, fin_n = t.profile_read(pv.PROF_FUSED_FINAL)
+    pro_ms, pro_n = t.profile_read(pv.PROF_FUSED_PROLOGUE)
+    t.profile(False)
+    elapsed = t1 - t0
+    px_iters = H * W * iters * args.steps
+    value = px_iters / elapsed / 1e6
+    log(f"fused: {elapsed * 1e3 / args.steps:.3f} ms/step, {value:.1f} Mpx-iter/s; "
+        f"iterate pass {it_ms / max(it_n, 1) * 1e3:.1f} us x {it_n}, final {fin_ms / max(fin_n, 1) * 1e3:.1f} us, "
+        f"prologue {pro_ms / max(pro_n, 1) * 1e3:.1f} us; flags seen {flags}")
+
+    avg_launch_s = it_ms / 1e3 / max(it_n, 1)
+    bytes_per_launch = BYTES_PER_PX_ITER * H * W
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_source_hash") == kernel_source_hash():
+            traffic = tr.get("bytes_per_launch")
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                    kernel="k_fu_iterate<false>", bytes_per_px_iter=BYTES_PER_PX_ITER,
+                    avg_launch_us=round(avg_launch_s * 1e6, 2), launches=it_n)
+
+    # the per-factor schedule on the same frames (row a13 baseline)
+    per_factor = None
+    if args.per_factor_steps > 0:
+        tp = make(pv.SCHED_PER_FACTOR)
+        for i in range(min(args.warmup, 1)):
+            step(tp, i, iters)
+        torch.cuda.synchronize()
+        tp.profile(True)
+        tp.profile_read(pv.PROF_PER_FACTOR)
+        a = time.perf_counter()
+        ns = min(args.per_factor_steps, args.steps)
+        for i in range(args.warmup, args.warmup + ns):
+            step(tp, i, iters)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        pf_ms, pf_n = tp.profile_read(pv.PROF_PER_FACTOR)
+        pf_value = H * W * iters * ns / (b - a) / 1e6
+        pf_launch = pf_ms / 1e3 / max(pf_n, 1)
+        per_factor = dict(value=round(pf_value, 1), unit="Mpixel-iter/s", steps=ns,
+                          iteration_us=round(pf_launch * 1e6, 1),
+                          frac_of_fused_bytes=round(BYTES_PER_PX_ITER * H * W / pf_launch / 1e9 / HBM_PEAK_GBS, 4),
+                          fused_speedup=round(value / pf_value, 2))
+        log(f"per-factor: {pf_value:.1f} Mpx-iter/s, iteration {pf_launch * 1e6:.1f} us")
+        tp.close()
+    t.close()
+    return dict(value=value, elapsed=elapsed, roofline=roofline, per_factor=per_factor, H=H, W=W, iters=iters)
+
+
+def cpu_baseline(iters: int):
+    """The FP64 oracle on the first frame of the same workload, `iters` iterations."""
+    import oracle
+    cam, I0, N0, frames, _ = vga_inputs(1)
+    cfg = oracle.config_for_camera(cam, **VGA_PARAMS)
+    o = oracle.Oracle(cfg)
+    o.set_keyframe(I0, N0)
+    a = time.perf_counter()
+    o.track(frames[0], iters)
+    b = time.perf_counter()
+    v = cam.H * cam.W * iters / (b - a) / 1e6
+    log(f"oracle: {b - a:.1f} s for {iters} iterations of 640x480 -> {v:.3f} Mpx-iter/s on {oracle.threads()} threads")
+    return dict(value=round(v, 4), unit="Mpixel-iter/s", cores=oracle.threads(), kind="oracle",
+                sample=f"frame 1 of the 640x480 sequence, {iters} GBP iterations ({b - a:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--iters", type=int, default=20)
+    ap.add_argument("--per-factor-steps", type=int, default=3)
+    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (single-GPU build)", file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        print("need --steps >= 1 and --warmup >= 0", file=sys.stderr)
+        sys.exit(2)
+
+    g = run_gpu(args)
+    cpu = None if args.no_cpu else cpu_baseline(args.cpu_iters)
+    out = {
+        "metric": "GBP Mpixel-iter/s at 640x480 + % HBM roofline; batched & fwd+adjoint vs plain",
+        "value": round(g["value"], 1),
+        "unit": "Mpixel-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(g["elapsed"] * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "vga640x480 piecewise-planar sequence, 20 GBP iterations per frame, fused schedule",
+                   "H": g["H"], "W": g["W"], "iters_per_frame": g["iters"], "state": "fp32 SoA, 123 planes",
+                   "sigma_P": VGA_PARAMS["sigma_P"], "huber_k": VGA_PARAMS["huber_k"]},
+        "roofline": g["roofline"],
+        "cpu_baseline": cpu,
+        "per_factor": g["per_factor"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,188 @@
+/*
+ * pixvod: per-pixel Gaussian Belief Propagation visual odometry and depth on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: PixVOD (arXiv 2606.03989). Every pixel holds a stacked variable of a
+ * camera pose in SE(3) and a log-depth (Sec. 3.3). Its photometric factor
+ * (Eq. distrb_photo) compares the keyframe intensity with the target frame
+ * sampled at the warp of Eq. (warp); a prior factor (Eq. prior) anchors pose
+ * and log-depth; camera-motion identity factors (Eq. regul) tie the poses of
+ * 4-neighbours together, and normal-integration factors (Eq. gbpni) tie their
+ * log-depths to a surface-normal map. Inference is synchronous Gaussian
+ * Belief Propagation with relinearisation at the current means (Sec. 3.4,
+ * Sec. 4.1) against a fixed keyframe (Sec. 3.5); the per-frame camera pose is
+ * the mean of the per-pixel poses (App. C.2, Eq. estimator_avg).
+ *
+ * Conventions shared by every entry point:
+ *   - Images are H x W row-major float32, pixel centres at integer (u, v).
+ *   - A pose tangent is [theta(3); rho(3)] with
+ *     Exp = [[R(theta), V(theta) rho], [0, 1]] (App. C.2, Eq. exp_err); the
+ *     per-pixel pose maps keyframe-camera points into the current camera.
+ *   - Every call returns a PIXVOD_* status; nothing throws across the ABI.
+ *     Arguments are validated before any GPU work is issued.
+ *   - Buffers passed in are owned by the caller. `where` says whether a
+ *     pointer is host memory (PIXVOD_HOST) or device memory on the context's
+ *     device (PIXVOD_DEVICE). Device pointers are used in stream order on the
+ *     context's stream.
+ *   - A context is used by one thread at a time; there is no internal locking.
+ *   - Numerical divergence is reported as a flag, not as an error.
+ */
+#ifndef PIXVOD_H
+#define PIXVOD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+enum {
+    PIXVOD_OK = 0,
+    PIXVOD_EINVAL = -1,   /* invalid argument */
+    PIXVOD_ESTATE = -2,   /* call not valid in the context's current state */
+    PIXVOD_EHIP = -3,     /* a HIP runtime call failed */
+    PIXVOD_ENOMEM = -4,   /* device allocation failed */
+    PIXVOD_ENODEV = -5    /* no usable gfx950 device */
+};
+
+/* memory location of a buffer argument */
+enum { PIXVOD_HOST = 0, PIXVOD_DEVICE = 1 };
+
+/* per-frame flags */
+enum {
+    PIXVOD_KEYFRAME_DUE = 1u,  /* re-anchoring test fired (Sec. 3.5) */
+    PIXVOD_DIVERGED = 2u,      /* non-finite state or a non-positive pivot */
+    PIXVOD_LOW_OVERLAP = 4u    /* valid-warp fraction below kf_min_valid_frac */
+};
+
+/* iteration schedules; both compute the same synchronous iteration */
+enum {
+    PIXVOD_SCHED_FUSED = 0,       /* one pass over the state per iteration */
+    PIXVOD_SCHED_PER_FACTOR = 1   /* one kernel per GBP step */
+};
+
+typedef struct pixvod_ctx pixvod_ctx;
+
+/* pinhole intrinsics in pixels */
+typedef struct {
+    float fx, fy, cx, cy;
+} pixvod_intrinsics;
+
+/* Factor strengths (Sec. 4.2: Lambda = sigma^-2 I, Huber threshold in
+ * whitened units) and tracking parameters. pixvod_default_params() fills the
+ * paper's leaf-level values (5e-3, 1, 4e-4, 1e-3, 400). */
+typedef struct {
+    float sigma_D;             /* photometric noise (intensity units) */
+    float sigma_P;             /* pose / log-depth prior */
+    float sigma_R;             /* camera-motion identity factor */
+    float sigma_N;             /* normal-integration factor */
+    float huber_k;             /* Huber threshold on the whitened residual */
+    float init_inv_depth;      /* inverse depth of every pixel at creation */
+    float prior_xi[6];         /* prior pose mean (identity by default) */
+    float prior_log_depth;     /* prior log-depth mean (0 = depth 1) */
+    int32_t kf_max_frames;     /* re-anchoring: frames per keyframe */
+    float kf_min_valid_frac;   /* re-anchoring: minimum overlap */
+    float damping;             /* message damping beta; only the per-factor
+                                * schedule supports beta != 0 */
+} pixvod_params;
+
+/* result of one tracked frame */
+typedef struct {
+    double xi_rel[6];          /* mean per-pixel pose, T_current<-keyframe */
+    double T_world[16];        /* row-major T_world<-current =
+                                * T_world<-keyframe * Exp(xi_rel)^-1 */
+    float* inv_depth;          /* caller buffer (H*W) or NULL: exp(-log depth) */
+    float* inv_depth_var;      /* caller buffer (H*W) or NULL: delta-method
+                                * variance of the inverse depth from the final
+                                * belief; NaN when n_iters == 0 */
+    int32_t out_where;         /* PIXVOD_HOST / PIXVOD_DEVICE for the two maps */
+    float valid_fraction;      /* pixels whose warp landed in the image during
+                                * the last iteration */
+    int32_t frames_since_keyframe;
+    uint32_t flags;            /* PIXVOD_KEYFRAME_DUE | DIVERGED | LOW_OVERLAP */
+} pixvod_track_out;
+
+/* Fills the paper's default parameters (Sec. 4.2) with init_inv_depth 1,
+ * kf_max_frames 150, kf_min_valid_frac 0.5, damping 0. */
+void pixvod_default_params(pixvod_params* params);
+
+/* Creates a context for H x W frames (H, W >= 2; fx, fy > 0) on the current
+ * HIP device. params == NULL selects the defaults. All device state is owned
+ * by the context: 123 float32 planes per pixel (pose 6, log-depth 1, four
+ * identity messages of 27 values and four normal messages of 2 values) in
+ * two ping-pong copies, plus the keyframe and frame inputs. Returns
+ * PIXVOD_ENODEV without a usable GPU, PIXVOD_ENOMEM if allocation fails. */
+int pixvod_create(int H, int W, const pixvod_intrinsics* K, const pixvod_params* params,
+                  pixvod_ctx** out_ctx);
+
+/* Releases every device allocation of the context. NULL is accepted. */
+int pixvod_destroy(pixvod_ctx* ctx);
+
+/* Uses `hip_stream` (a hipStream_t, e.g. torch's current stream) for all
+ * later work; NULL restores the context's own stream. */
+int pixvod_set_stream(pixvod_ctx* ctx, void* hip_stream);
+
+/* Selects PIXVOD_SCHED_FUSED (default) or PIXVOD_SCHED_PER_FACTOR.
+ * PIXVOD_EINVAL for the fused schedule when params.damping != 0. */
+int pixvod_set_schedule(pixvod_ctx* ctx, int schedule);
+
+/* Keyframe anchoring (Sec. 3.5): `img` (H*W) becomes the reference image and
+ * `normals` (H*W*3, unit normals in the keyframe camera frame) define the
+ * normal-integration targets of Eq. (gbpni). Pose linearisation points are
+ * reset to identity and every message to zero; log-depths are kept. After a
+ * tracked frame, the world pose of the keyframe becomes that frame's world
+ * pose (re-anchoring on the frame just tracked). */
+int pixvod_set_keyframe(pixvod_ctx* ctx, const float* img, const float* normals, int where);
+
+/* Optional per-pixel photometric sigma map (H*W); NULL restores the constant
+ * params.sigma_D. */
+int pixvod_set_sigma_map(pixvod_ctx* ctx, const float* sigma_D_map, int where);
+
+/* Tracks one target frame (H*W): n_iters >= 0 synchronous GBP iterations
+ * warm-started from the previous frame's state (Sec. 4.3), then the pose
+ * estimate, output maps, keyframe test and flags. Returns after the pose is
+ * on the host; device output maps are written in stream order.
+ * PIXVOD_ESTATE before the first pixvod_set_keyframe. */
+int pixvod_track(pixvod_ctx* ctx, const float* frame, int where, int n_iters,
+                 pixvod_track_out* out);
+
+/* Runs n_iters iterations on the last staged frame without per-frame
+ * bookkeeping (benchmarks and tests). */
+int pixvod_iterate(pixvod_ctx* ctx, int n_iters);
+
+/* State exchange: 123 planes of H*W float32 in plane-major order
+ * [pose 0..5, log-depth, for d in {left, right, up, down}: identity message
+ * eta(6) + Lambda upper-packed row-major(21), for d: normal eta, lambda].
+ * Slot d of pixel i holds the message from the factor on the edge towards
+ * the neighbour in direction d; slots of edges that leave the image are 0. */
+int pixvod_state_bytes(const pixvod_ctx* ctx, size_t* bytes);
+int pixvod_get_state(pixvod_ctx* ctx, void* dst, int where);
+int pixvod_set_state(pixvod_ctx* ctx, const void* src, int where);
+
+/* Kernel timing for benchmarks. With profiling enabled, the context records
+ * a HIP event pair on its stream around every launch of the passes below;
+ * pixvod_profile_read() waits for the stream, returns the summed duration in
+ * milliseconds and the launch count of one pass kind, and resets that kind. */
+enum {
+    PIXVOD_PROF_FUSED_ITERATE = 0,    /* one fused iteration pass (not the last of a frame) */
+    PIXVOD_PROF_FUSED_FINAL = 1,      /* the last fused pass of a frame */
+    PIXVOD_PROF_FUSED_PROLOGUE = 2,   /* the per-frame prologue of the fused schedule */
+    PIXVOD_PROF_PER_FACTOR = 3,       /* one per-factor iteration (three kernels) */
+    PIXVOD_PROF_KINDS = 4
+};
+int pixvod_profile_enable(pixvod_ctx* ctx, int enable);
+int pixvod_profile_read(pixvod_ctx* ctx, int kind, double* total_ms, int64_t* launches);
+
+/* Per-context message of the last failure; ctx == NULL gives the last
+ * failure of a call that had no context (e.g. pixvod_create). */
+const char* pixvod_last_error(const pixvod_ctx* ctx);
+
+/* Library version string. */
+const char* pixvod_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIXVOD_H */

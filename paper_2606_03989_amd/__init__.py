@@ -1,0 +1,232 @@
+"""Python binding of libpixvod: per-pixel GBP visual odometry and depth on MI355X.
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+libpixvod.so. torch is imported before the library is loaded so that torch
+and libpixvod share one HIP runtime; torch tensors on the GPU are passed as
+device pointers on the context's stream, numpy arrays and CPU tensors as host
+pointers.
+
+The library must be built (``python -m paper_2606_03989_amd.build`` or
+``__graft_entry__.build()``); importing this package without it raises.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+import torch  # noqa: F401  (shared HIP runtime; must precede the library load)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpixvod.so")
+
+OK, EINVAL, ESTATE, EHIP, ENOMEM, ENODEV = 0, -1, -2, -3, -4, -5
+HOST, DEVICE = 0, 1
+KEYFRAME_DUE, DIVERGED, LOW_OVERLAP = 1, 2, 4
+SCHED_FUSED, SCHED_PER_FACTOR = 0, 1
+PROF_FUSED_ITERATE, PROF_FUSED_FINAL, PROF_FUSED_PROLOGUE, PROF_PER_FACTOR = 0, 1, 2, 3
+N_PLANES = 123
+
+
+class PixvodError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pixvod error {code}: {msg}")
+        self.code = code
+
+
+class Intrinsics(C.Structure):
+    _fields_ = [("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float)]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("sigma_D", C.c_float), ("sigma_P", C.c_float), ("sigma_R", C.c_float), ("sigma_N", C.c_float),
+        ("huber_k", C.c_float), ("init_inv_depth", C.c_float), ("prior_xi", C.c_float * 6),
+        ("prior_log_depth", C.c_float), ("kf_max_frames", C.c_int32), ("kf_min_valid_frac", C.c_float),
+        ("damping", C.c_float),
+    ]
+
+
+class TrackOut(C.Structure):
+    _fields_ = [
+        ("xi_rel", C.c_double * 6), ("T_world", C.c_double * 16),
+        ("inv_depth", C.c_void_p), ("inv_depth_var", C.c_void_p), ("out_where", C.c_int32),
+        ("valid_fraction", C.c_float), ("frames_since_keyframe", C.c_int32), ("flags", C.c_uint32),
+    ]
+
+
+_lib: Optional[C.CDLL] = None
+
+# every entry point declared in include/pixvod.h, with its ctypes signature
+_SIGNATURES = {
+    "pixvod_default_params": (None, [C.POINTER(Params)]),
+    "pixvod_create": (C.c_int, [C.c_int, C.c_int, C.POINTER(Intrinsics), C.POINTER(Params), C.POINTER(C.c_void_p)]),
+    "pixvod_destroy": (C.c_int, [C.c_void_p]),
+    "pixvod_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "pixvod_set_schedule": (C.c_int, [C.c_void_p, C.c_int]),
+    "pixvod_set_keyframe": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "pixvod_set_sigma_map": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "pixvod_track": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.POINTER(TrackOut)]),
+    "pixvod_iterate": (C.c_int, [C.c_void_p, C.c_int]),
+    "pixvod_state_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "pixvod_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "pixvod_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "pixvod_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
+    "pixvod_profile_read": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "pixvod_last_error": (C.c_char_p, [C.c_void_p]),
+    "pixvod_version": (C.c_char_p, []),
+}
+
+
+def lib() -> C.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libpixvod.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def default_params(**overrides) -> Params:
+    p = Params()
+    lib().pixvod_default_params(C.byref(p))
+    for k, v in overrides.items():
+        if k == "prior_xi":
+            for i in range(6):
+                p.prior_xi[i] = float(v[i])
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def _check(rc: int, ctx=None):
+    if rc != OK:
+        msg = lib().pixvod_last_error(ctx)
+        raise PixvodError(rc, msg.decode() if msg else "")
+
+
+def _ptr(a, dtype=np.float32):
+    """(pointer, where, keepalive) for a numpy array or torch tensor."""
+    if isinstance(a, torch.Tensor):
+        if a.dtype != torch.float32:
+            raise TypeError("float32 tensors required")
+        if not a.is_contiguous():
+            raise ValueError("contiguous tensors required")
+        return a.data_ptr(), (DEVICE if a.is_cuda else HOST), a
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    return arr.ctypes.data, HOST, arr
+
+
+class Tracker:
+    """One image sequence: keyframe, target frames and the GBP state on the GPU."""
+
+    def __init__(self, H: int, W: int, K, params: Optional[Params] = None, **overrides):
+        self.H, self.W = int(H), int(W)
+        if params is None:
+            params = default_params(**overrides)
+        self.params = params
+        Kc = Intrinsics(*[float(x) for x in K])
+        h = C.c_void_p()
+        _check(lib().pixvod_create(self.H, self.W, C.byref(Kc), C.byref(params), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pixvod_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_stream(self, stream=None):
+        s = None if stream is None else C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else stream)
+        _check(lib().pixvod_set_stream(self._h, s), self._h)
+
+    def set_schedule(self, schedule: int):
+        _check(lib().pixvod_set_schedule(self._h, int(schedule)), self._h)
+
+    def set_keyframe(self, img, normals):
+        pi, wi, ki = _ptr(img)
+        pn, wn, kn = _ptr(normals)
+        if wi != wn:
+            raise ValueError("image and normals must live in the same memory")
+        _check(lib().pixvod_set_keyframe(self._h, C.c_void_p(pi), C.c_void_p(pn), wi), self._h)
+
+    def set_sigma_map(self, sigma):
+        if sigma is None:
+            _check(lib().pixvod_set_sigma_map(self._h, None, HOST), self._h)
+            return
+        p, w, k = _ptr(sigma)
+        _check(lib().pixvod_set_sigma_map(self._h, C.c_void_p(p), w), self._h)
+
+    def track(self, frame, n_iters: int, maps: bool = True, out_device: bool = False):
+        """Tracks one frame; returns pose, world pose, flags and (optionally)
+        the inverse-depth and variance maps (numpy, or torch CUDA tensors with
+        out_device=True)."""
+        pf, wf, kf = _ptr(frame)
+        out = TrackOut()
+        inv = var = None
+        if maps:
+            if out_device:
+                inv = torch.empty((self.H, self.W), dtype=torch.float32, device="cuda")
+                var = torch.empty((self.H, self.W), dtype=torch.float32, device="cuda")
+                out.inv_depth, out.inv_depth_var, out.out_where = inv.data_ptr(), var.data_ptr(), DEVICE
+            else:
+                inv = np.empty((self.H, self.W), np.float32)
+                var = np.empty((self.H, self.W), np.float32)
+                out.inv_depth, out.inv_depth_var, out.out_where = inv.ctypes.data, var.ctypes.data, HOST
+        else:
+            out.out_where = HOST
+        _check(lib().pixvod_track(self._h, C.c_void_p(pf), wf, int(n_iters), C.byref(out)), self._h)
+        return dict(xi=np.array(out.xi_rel[:]), T_world=np.array(out.T_world[:]).reshape(4, 4),
+                    valid_fraction=float(out.valid_fraction),
+                    frames_since_keyframe=int(out.frames_since_keyframe), flags=int(out.flags),
+                    inv_depth=inv, inv_depth_var=var)
+
+    def iterate(self, n: int):
+        _check(lib().pixvod_iterate(self._h, int(n)), self._h)
+
+    def profile(self, enable: bool = True):
+        _check(lib().pixvod_profile_enable(self._h, 1 if enable else 0), self._h)
+
+    def profile_read(self, kind: int):
+        """(total milliseconds, launches) of one timed pass kind; resets it."""
+        ms, n = C.c_double(), C.c_int64()
+        _check(lib().pixvod_profile_read(self._h, int(kind), C.byref(ms), C.byref(n)), self._h)
+        return ms.value, n.value
+
+    def state_bytes(self) -> int:
+        n = C.c_size_t()
+        _check(lib().pixvod_state_bytes(self._h, C.byref(n)), self._h)
+        return n.value
+
+    def get_state(self) -> np.ndarray:
+        """State as (123, H, W) float32 (plane-major exchange layout)."""
+        s = np.empty((N_PLANES, self.H, self.W), np.float32)
+        _check(lib().pixvod_get_state(self._h, C.c_void_p(s.ctypes.data), HOST), self._h)
+        return s
+
+    def set_state(self, s):
+        p, w, k = _ptr(s)
+        _check(lib().pixvod_set_state(self._h, C.c_void_p(p), w), self._h)
+
+
+def version() -> str:
+    return lib().pixvod_version().decode()

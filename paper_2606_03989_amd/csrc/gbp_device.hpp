@@ -1,0 +1,530 @@
+// Per-pixel GBP algebra for gfx950, FP64 in registers.
+//
+// Method: PixVOD (arXiv 2606.03989). Storage is FP32 structure-of-arrays
+// planes; every per-pixel 6x6 / 7x7 solve, marginalisation and message is
+// evaluated in double precision (the information matrices span ~1 .. 1e8).
+//
+// Tangent ordering [theta(3); rho(3); logdepth], Exp of Eq. (exp_err),
+// perturbations on the right (Eq. var), information form (eta, Lambda).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pv {
+
+// ---------------------------------------------------------------------------
+// plane indices of the 123-plane state
+constexpr int P_TAU = 0;                 // 6 planes
+constexpr int P_ELL = 6;
+constexpr int P_MID = 7;                 // 4 x 27: eta(6) + upper-packed Lambda(21)
+constexpr int P_MN = 115;                // 4 x 2: eta, lambda
+constexpr int N_PLANES = 123;
+constexpr int MID_STRIDE = 27;
+
+enum { DIR_L = 0, DIR_R = 1, DIR_U = 2, DIR_D = 3 };
+
+__host__ __device__ constexpr int opposite(int d) { return d ^ 1; }
+__host__ __device__ constexpr int s6(int r, int c) {
+    return r <= c ? r * 6 - r * (r - 1) / 2 + (c - r) : c * 6 - c * (c - 1) / 2 + (r - c);
+}
+__host__ __device__ constexpr int s7(int r, int c) {
+    return r <= c ? r * 7 - r * (r - 1) / 2 + (c - r) : c * 7 - c * (c - 1) / 2 + (r - c);
+}
+
+// ---------------------------------------------------------------------------
+// frame geometry and factor strengths, passed by value to every kernel
+struct Geo {
+    int H, W;
+    int pitch;            // floats per row of every plane
+    long plane;           // floats per plane (H * pitch)
+    double fx, fy, cx, cy;
+};
+
+struct Strengths {
+    double lamP;          // prior
+    double lamR;          // identity
+    double lamN;          // normal integration
+    double lamD;          // photometric, used when no sigma map is bound
+    double huber_k;
+    double prior_ell;
+    double prior_R[9];    // Exp(prior_xi)^-1 rotation
+    double prior_t[3];    // Exp(prior_xi)^-1 translation
+    int prior_is_identity;
+    int has_sigma_map;
+};
+
+// inputs that stay fixed for a keyframe / a frame
+struct Inputs {
+    const float* Is;      // keyframe image
+    const float* cxt;     // normal targets towards the right neighbour
+    const float* cyt;     // normal targets towards the lower neighbour
+    const float* sigD;    // per-pixel sigma_D (valid if has_sigma_map)
+    const float* It;      // target frame
+    const float* Gx;      // its central-difference gradients
+    const float* Gy;
+};
+
+// ---------------------------------------------------------------------------
+// SE(3)
+
+__device__ inline void skew_mul(const double w[3], const double v[3], double out[3]) {
+    out[0] = w[1] * v[2] - w[2] * v[1];
+    out[1] = w[2] * v[0] - w[0] * v[2];
+    out[2] = w[0] * v[1] - w[1] * v[0];
+}
+
+// R = I + A W + B W^2 and V = I + B W + C W^2 with W = [theta]x
+__device__ inline void se3_exp(const double xi[6], double R[9], double t[3]) {
+    const double w0 = xi[0], w1 = xi[1], w2 = xi[2];
+    const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
+    double A, B, C;
+    if (th2 < 1e-2) {
+        const double t4 = th2 * th2, t6 = t4 * th2, t8 = t4 * t4;
+        A = 1.0 - th2 * (1.0 / 6.0) + t4 * (1.0 / 120.0) - t6 * (1.0 / 5040.0) + t8 * (1.0 / 362880.0);
+        B = 0.5 - th2 * (1.0 / 24.0) + t4 * (1.0 / 720.0) - t6 * (1.0 / 40320.0) + t8 * (1.0 / 3628800.0);
+        C = 1.0 / 6.0 - th2 * (1.0 / 120.0) + t4 * (1.0 / 5040.0) - t6 * (1.0 / 362880.0) + t8 * (1.0 / 39916800.0);
+    } else {
+        const double th = sqrt(th2);
+        double s, c;
+        sincos(th, &s, &c);
+        const double sh = sin(0.5 * th);
+        A = s / th;
+        B = 2.0 * sh * sh / th2;
+        C = (th - s) / (th2 * th);
+    }
+    // W^2 = w w^T - th2 I
+    const double W2[9] = {w0 * w0 - th2, w0 * w1, w0 * w2,
+                          w1 * w0, w1 * w1 - th2, w1 * w2,
+                          w2 * w0, w2 * w1, w2 * w2 - th2};
+    const double Wm[9] = {0.0, -w2, w1, w2, 0.0, -w0, -w1, w0, 0.0};
+    double V[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const double I = (k % 4 == 0) ? 1.0 : 0.0;
+        R[k] = I + A * Wm[k] + B * W2[k];
+        V[k] = I + B * Wm[k] + C * W2[k];
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) t[r] = V[r * 3] * xi[3] + V[r * 3 + 1] * xi[4] + V[r * 3 + 2] * xi[5];
+}
+
+__device__ inline void so3_log(const double R[9], double w[3]) {
+    const double v0 = R[7] - R[5], v1 = R[2] - R[6], v2 = R[3] - R[1];
+    const double s = 0.5 * sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+    const double c = 0.5 * (R[0] + R[4] + R[8] - 1.0);
+    const double th = atan2(s, c);
+    double f;
+    if (th < 1e-4) {
+        const double t2 = th * th;
+        f = 0.5 * (1.0 + t2 * (1.0 / 6.0) + t2 * t2 * (7.0 / 360.0));
+    } else if (th < 3.14149265358979) {
+        f = th / (2.0 * sin(th));
+    } else {
+        // near pi: axis from the diagonal (not reached by tracking motions)
+        double n[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const double d = (R[i * 4] + 1.0) * 0.5;
+            n[i] = sqrt(d > 0.0 ? d : 0.0);
+        }
+        const int k = (n[0] >= n[1] && n[0] >= n[2]) ? 0 : (n[1] >= n[2] ? 1 : 2);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            if (i != k) n[i] = (R[i * 3 + k] + R[k * 3 + i]) / (4.0 * n[k]);
+        double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        if (n[0] * v0 + n[1] * v1 + n[2] * v2 < 0.0) nn = -nn;
+        w[0] = th * n[0] / nn;
+        w[1] = th * n[1] / nn;
+        w[2] = th * n[2] / nn;
+        return;
+    }
+    w[0] = f * v0;
+    w[1] = f * v1;
+    w[2] = f * v2;
+}
+
+// xi = Log([R | t]); translation part rho = V^-1 t, V^-1 = I - W/2 + D W^2
+__device__ inline void se3_log(const double R[9], const double t[3], double xi[6]) {
+    so3_log(R, xi);
+    const double w0 = xi[0], w1 = xi[1], w2 = xi[2];
+    const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
+    double D;
+    if (th2 < 1e-2) {
+        const double t4 = th2 * th2, t6 = t4 * th2, t8 = t4 * t4;
+        D = 1.0 / 12.0 + th2 * (1.0 / 720.0) + t4 * (1.0 / 30240.0) + t6 * (1.0 / 1209600.0) +
+            t8 * (1.0 / 47900160.0);
+    } else {
+        const double th = sqrt(th2), sh = sin(0.5 * th);
+        D = (1.0 - th * sin(th) / (4.0 * sh * sh)) / th2;
+    }
+    double wt[3], wwt[3];
+    skew_mul(xi, t, wt);
+    skew_mul(xi, wt, wwt);
+    xi[3] = t[0] - 0.5 * wt[0] + D * wwt[0];
+    xi[4] = t[1] - 0.5 * wt[1] + D * wwt[1];
+    xi[5] = t[2] - 0.5 * wt[2] + D * wwt[2];
+}
+
+// [Ro | to] = [Ra | ta] * [Rb | tb]
+__device__ inline void se3_compose(const double Ra[9], const double ta[3], const double Rb[9],
+                                   const double tb[3], double Ro[9], double to[3]) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            Ro[r * 3 + c] = Ra[r * 3] * Rb[c] + Ra[r * 3 + 1] * Rb[3 + c] + Ra[r * 3 + 2] * Rb[6 + c];
+        to[r] = Ra[r * 3] * tb[0] + Ra[r * 3 + 1] * tb[1] + Ra[r * 3 + 2] * tb[2] + ta[r];
+    }
+}
+
+// Log([Rj | tj]^-1 [Ri | ti]): the identity-factor residual of Eq. (regul)
+__device__ inline void se3_between(const double Rj[9], const double tj[3], const double Ri[9],
+                                   const double ti[3], double r[6]) {
+    double R[9], t[3], d[3] = {ti[0] - tj[0], ti[1] - tj[1], ti[2] - tj[2]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) R[a * 3 + c] = Rj[a] * Ri[c] + Rj[3 + a] * Ri[3 + c] + Rj[6 + a] * Ri[6 + c];
+        t[a] = Rj[a] * d[0] + Rj[3 + a] * d[1] + Rj[6 + a] * d[2];
+    }
+    se3_log(R, t, r);
+}
+
+// ---------------------------------------------------------------------------
+// small symmetric linear algebra, packed upper storage
+
+// in-place LDL^T-free Cholesky of a packed 6x6 SPD matrix; A <- L (lower in the
+// same packed slots, L(r,c) stored at s6(c,r)); returns false on a
+// non-positive pivot. inv_diag receives 1/L(k,k).
+__device__ inline bool chol6(double A[21], double inv_diag[6]) {
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        double d = A[s6(j, j)];
+#pragma unroll
+        for (int k = 0; k < j; ++k) d -= A[s6(j, k)] * A[s6(j, k)];
+        ok = ok && (d > 0.0);
+        const double l = sqrt(d > 0.0 ? d : 1e-300);
+        const double il = 1.0 / l;
+        A[s6(j, j)] = l;
+        inv_diag[j] = il;
+#pragma unroll
+        for (int i = j + 1; i < 6; ++i) {
+            double s = A[s6(i, j)];
+#pragma unroll
+            for (int k = 0; k < j; ++k) s -= A[s6(i, k)] * A[s6(j, k)];
+            A[s6(i, j)] = s * il;
+        }
+    }
+    return ok;
+}
+
+__device__ inline void chol6_solve(const double L[21], const double inv_diag[6], double b[6]) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        double s = b[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) s -= L[s6(i, k)] * b[k];
+        b[i] = s * inv_diag[i];
+    }
+#pragma unroll
+    for (int i = 5; i >= 0; --i) {
+        double s = b[i];
+#pragma unroll
+        for (int k = i + 1; k < 6; ++k) s -= L[s6(k, i)] * b[k];
+        b[i] = s * inv_diag[i];
+    }
+}
+
+// inverse of the SPD matrix from its Cholesky factor: Ainv (packed) = L^-T L^-1
+__device__ inline void chol6_inverse(const double L[21], const double inv_diag[6], double Ai[21]) {
+    // X = L^-1 (lower triangular), packed the same way as L
+    double X[21];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        X[s6(j, j)] = inv_diag[j];
+#pragma unroll
+        for (int i = j + 1; i < 6; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = j; k < i; ++k) s -= L[s6(i, k)] * X[s6(k, j)];
+            X[s6(i, j)] = s * inv_diag[i];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+        for (int c = r; c < 6; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = c; k < 6; ++k) s += X[s6(k, r)] * X[s6(k, c)];
+            Ai[s6(r, c)] = s;
+        }
+}
+
+__device__ inline bool chol7(double A[28], double inv_diag[7]) {
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        double d = A[s7(j, j)];
+#pragma unroll
+        for (int k = 0; k < j; ++k) d -= A[s7(j, k)] * A[s7(j, k)];
+        ok = ok && (d > 0.0);
+        const double l = sqrt(d > 0.0 ? d : 1e-300);
+        const double il = 1.0 / l;
+        A[s7(j, j)] = l;
+        inv_diag[j] = il;
+#pragma unroll
+        for (int i = j + 1; i < 7; ++i) {
+            double s = A[s7(i, j)];
+#pragma unroll
+            for (int k = 0; k < j; ++k) s -= A[s7(i, k)] * A[s7(j, k)];
+            A[s7(i, j)] = s * il;
+        }
+    }
+    return ok;
+}
+
+__device__ inline void chol7_solve(const double L[28], const double inv_diag[7], double b[7]) {
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        double s = b[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) s -= L[s7(i, k)] * b[k];
+        b[i] = s * inv_diag[i];
+    }
+#pragma unroll
+    for (int i = 6; i >= 0; --i) {
+        double s = b[i];
+#pragma unroll
+        for (int k = i + 1; k < 7; ++k) s -= L[s7(k, i)] * b[k];
+        b[i] = s * inv_diag[i];
+    }
+}
+
+// [A^-1]_66 from the Cholesky factor: |L^-T e_6|^2 = 1 / L66^2 (last row of L^-1
+// has a single entry in its last column)
+__device__ inline double chol7_var_last(const double inv_diag[7]) { return inv_diag[6] * inv_diag[6]; }
+
+// ---------------------------------------------------------------------------
+// photometric and prior factors
+
+__device__ inline float plane_at(const float* p, const Geo& g, int u, int v) {
+    return p[(long)v * g.pitch + u];
+}
+
+// bilinear samples of I_t, G_x, G_y at (x, y) in [0, W-1] x [0, H-1]
+__device__ inline void sample3(const Inputs& in, const Geo& g, double x, double y, double& I,
+                               double& gx, double& gy) {
+    int x0 = (int)floor(x), y0 = (int)floor(y);
+    x0 = x0 > g.W - 2 ? g.W - 2 : (x0 < 0 ? 0 : x0);
+    y0 = y0 > g.H - 2 ? g.H - 2 : (y0 < 0 ? 0 : y0);
+    const double fx = x - x0, fy = y - y0;
+    const long o = (long)y0 * g.pitch + x0;
+    const long o2 = o + g.pitch;
+    const double w00 = (1.0 - fx) * (1.0 - fy), w10 = fx * (1.0 - fy), w01 = (1.0 - fx) * fy, w11 = fx * fy;
+    I = (1.0 - fy) * ((1.0 - fx) * in.It[o] + fx * in.It[o + 1]) + fy * ((1.0 - fx) * in.It[o2] + fx * in.It[o2 + 1]);
+    gx = (1.0 - fy) * ((1.0 - fx) * in.Gx[o] + fx * in.Gx[o + 1]) + fy * ((1.0 - fx) * in.Gx[o2] + fx * in.Gx[o2 + 1]);
+    gy = (1.0 - fy) * ((1.0 - fx) * in.Gy[o] + fx * in.Gy[o + 1]) + fy * ((1.0 - fx) * in.Gy[o2] + fx * in.Gy[o2 + 1]);
+    (void)w00; (void)w10; (void)w01; (void)w11;
+}
+
+constexpr double WARP_EPS = 1e-3;
+
+// Adds the photometric factor of pixel (u, v) (Eq. distrb_photo, warp of
+// Eq. warp, Huber covariance weighting) and the prior factor (Eq. prior) at
+// the linearisation point (R, t) = Exp(tau), ell to (L, eta). Returns the
+// valid-warp flag.
+__device__ inline bool unary_factors(const Geo& g, const Strengths& s, const Inputs& in, int u, int v,
+                                     const double tau[6], const double R[9], const double t[3],
+                                     double ell, double L[28], double eta[7]) {
+#pragma unroll
+    for (int k = 0; k < 28; ++k) L[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) eta[k] = 0.0;
+
+    // --- photometric
+    const double q0 = ((double)u - g.cx) / g.fx, q1 = ((double)v - g.cy) / g.fy;
+    const double rho = exp(-ell);
+    const double a0 = R[0] * q0 + R[1] * q1 + R[2] + rho * t[0];
+    const double a1 = R[3] * q0 + R[4] * q1 + R[5] + rho * t[1];
+    const double a2 = R[6] * q0 + R[7] * q1 + R[8] + rho * t[2];
+    bool valid = false;
+    if (a2 > 0.0) {
+        const double iz = 1.0 / a2;
+        const double wx = g.fx * a0 * iz + g.cx, wy = g.fy * a1 * iz + g.cy;
+        if (wx >= -WARP_EPS && wx <= (g.W - 1) + WARP_EPS && wy >= -WARP_EPS && wy <= (g.H - 1) + WARP_EPS) {
+            valid = true;
+            const double x = fmin(fmax(wx, 0.0), (double)(g.W - 1));
+            const double y = fmin(fmax(wy, 0.0), (double)(g.H - 1));
+            double It, gx, gy;
+            sample3(in, g, x, y, It, gx, gy);
+            const long pix = (long)v * g.pitch + u;
+            const double r = (double)in.Is[pix] - It;
+            // c = -g^T dw/da  (row 3-vector)
+            const double c0 = -gx * g.fx * iz, c1 = -gy * g.fy * iz;
+            const double c2 = (gx * g.fx * a0 + gy * g.fy * a1) * iz * iz;
+            // J_theta = c * (-R [q]x) = -(R^T c) x q ... computed as (R^T c) cross-form:
+            // -R[q]x d = -R (q x d)  => c.(-R (q x d)) = -(R^T c).(q x d) = -((R^T c) x ... )
+            const double b0 = R[0] * c0 + R[3] * c1 + R[6] * c2;   // R^T c
+            const double b1 = R[1] * c0 + R[4] * c1 + R[7] * c2;
+            const double b2 = R[2] * c0 + R[5] * c1 + R[8] * c2;
+            // c.(-R (q x d)) = -b.(q x d) = -(b x q).d ... b.(q x d) = d.(b x q)
+            double J[7];
+            J[0] = -(b1 * 1.0 - b2 * q1);
+            J[1] = -(b2 * q0 - b0 * 1.0);
+            J[2] = -(b0 * q1 - b1 * q0);
+            J[3] = rho * b0;
+            J[4] = rho * b1;
+            J[5] = rho * b2;
+            J[6] = -rho * (c0 * t[0] + c1 * t[1] + c2 * t[2]);
+            const double lamD = s.has_sigma_map ? 1.0 / ((double)in.sigD[pix] * (double)in.sigD[pix]) : s.lamD;
+            const double M = fabs(r) * sqrt(lamD);
+            const double kappa = (M <= s.huber_k) ? 1.0 : (2.0 * s.huber_k / M - (s.huber_k * s.huber_k) / (M * M));
+            const double w = kappa * lamD;
+#pragma unroll
+            for (int a = 0; a < 7; ++a) {
+                const double wJa = w * J[a];
+                eta[a] -= wJa * r;
+#pragma unroll
+                for (int b = a; b < 7; ++b) L[s7(a, b)] += wJa * J[b];
+            }
+        }
+    }
+
+    // --- prior: r = [Log(Exp(prior)^-1 Exp(tau)); ell - prior_ell],
+    //     J = blockdiag(I + ad/2 + ad^2/12, 1)
+    double rp[6];
+    if (s.prior_is_identity) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) rp[k] = tau[k];
+    } else {
+        double Rr[9], tr[3];
+        se3_compose(s.prior_R, s.prior_t, R, t, Rr, tr);
+        se3_log(Rr, tr, rp);
+    }
+    // ad = [[W, 0], [P, W]] with W = [theta]x, P = [rho]x
+    double Jp[36];
+    {
+        const double w0 = rp[0], w1 = rp[1], w2 = rp[2], p0 = rp[3], p1 = rp[4], p2 = rp[5];
+        const double Wm[9] = {0.0, -w2, w1, w2, 0.0, -w0, -w1, w0, 0.0};
+        const double Pm[9] = {0.0, -p2, p1, p2, 0.0, -p0, -p1, p0, 0.0};
+        double WW[9], PW[9], WP[9];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                WW[r * 3 + c] = Wm[r * 3] * Wm[c] + Wm[r * 3 + 1] * Wm[3 + c] + Wm[r * 3 + 2] * Wm[6 + c];
+                PW[r * 3 + c] = Pm[r * 3] * Wm[c] + Pm[r * 3 + 1] * Wm[3 + c] + Pm[r * 3 + 2] * Wm[6 + c];
+                WP[r * 3 + c] = Wm[r * 3] * Pm[c] + Wm[r * 3 + 1] * Pm[3 + c] + Wm[r * 3 + 2] * Pm[6 + c];
+            }
+        // ad^2 = [[W^2, 0], [PW + WP, W^2]]
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double I = (r == c) ? 1.0 : 0.0;
+                const double top = I + 0.5 * Wm[r * 3 + c] + WW[r * 3 + c] * (1.0 / 12.0);
+                Jp[r * 6 + c] = top;
+                Jp[r * 6 + c + 3] = 0.0;
+                Jp[(r + 3) * 6 + c] = 0.5 * Pm[r * 3 + c] + (PW[r * 3 + c] + WP[r * 3 + c]) * (1.0 / 12.0);
+                Jp[(r + 3) * 6 + c + 3] = top;
+            }
+    }
+    const double lamP = s.lamP;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double rk = lamP * rp[k];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+            const double lJa = lamP * Jp[k * 6 + a];
+            eta[a] -= Jp[k * 6 + a] * rk;
+#pragma unroll
+            for (int b = a; b < 6; ++b) L[s7(a, b)] += lJa * Jp[k * 6 + b];
+        }
+    }
+    eta[6] -= lamP * (ell - s.prior_ell);
+    L[s7(6, 6)] += lamP;
+    return valid;
+}
+
+// ---------------------------------------------------------------------------
+// marginals of a pixel belief
+
+// pose marginal (depth eliminated): P = L_pp - L_p6 L_6p / L_66
+__device__ inline void pose_marginal(const double L[28], const double eta[7], double P[21], double p[6]) {
+    const double i66 = 1.0 / L[s7(6, 6)];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+        const double lr = L[s7(r, 6)] * i66;
+        p[r] = eta[r] - lr * eta[6];
+#pragma unroll
+        for (int c = r; c < 6; ++c) P[s6(r, c)] = L[s7(r, c)] - lr * L[s7(c, 6)];
+    }
+}
+
+// depth marginal (pose eliminated): D = L_66 - L_6p L_pp^-1 L_p6
+__device__ inline bool depth_marginal(const double L[28], const double eta[7], double& D, double& dv) {
+    double A[21], idg[6], y[6], z[6];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+#pragma unroll
+        for (int c = r; c < 6; ++c) A[s6(r, c)] = L[s7(r, c)];
+        y[r] = L[s7(r, 6)];
+        z[r] = eta[r];
+    }
+    const bool ok = chol6(A, idg);
+    chol6_solve(A, idg, y);
+    chol6_solve(A, idg, z);
+    double sy = 0.0, sz = 0.0;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+        sy += L[s7(r, 6)] * y[r];
+        sz += y[r] * eta[r];
+    }
+    D = L[s7(6, 6)] - sy;
+    dv = eta[6] - sz;
+    return ok;
+}
+
+// ---------------------------------------------------------------------------
+// factor-to-variable messages, split into the part the sender computes from
+// its variable-to-factor message (the "partial", independent of the
+// receiver's linearisation point) and the receiver's completion with the
+// factor residual at both linearisation points.
+//
+// Identity factor (Eq. regul) with Jacobians +I / -I: for the sender's
+// variable-to-factor pose marginal (V, v) and A = lamR I + V,
+//   Lambda' = lamR I - lamR^2 A^-1,   h = lamR A^-1 v,   eta' = h - Lambda' r.
+__device__ inline bool identity_partial(double lamR, double V[21], const double v[6], double Lp[21],
+                                        double h[6]) {
+    double idg[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) V[s6(k, k)] += lamR;
+    const bool ok = chol6(V, idg);
+    double Ai[21];
+    chol6_inverse(V, idg, Ai);
+    const double l2 = lamR * lamR;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) s += Ai[s6(r, c)] * v[c];
+        h[r] = lamR * s;
+#pragma unroll
+        for (int c = r; c < 6; ++c) Lp[s6(r, c)] = (r == c ? lamR : 0.0) - l2 * Ai[s6(r, c)];
+    }
+    return ok;
+}
+
+// Normal-integration factor (Eq. gbpni): sender's depth marginal (ls, vs),
+//   lambda' = lamN ls / (lamN + ls),  h = lamN vs / (lamN + ls),
+//   eta' = h - lambda' r_recv with r_recv the residual as seen by the receiver.
+__device__ inline void normal_partial(double lamN, double ls, double vs, double& lp, double& h) {
+    const double inv = 1.0 / (lamN + ls);
+    lp = lamN * ls * inv;
+    h = lamN * vs * inv;
+}
+
+}  // namespace pv

@@ -1,0 +1,33 @@
+// Launchers of the GBP kernels (host-side declarations).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pv {
+
+struct Geo;
+struct Strengths;
+struct Inputs;
+
+hipError_t launch_frame_prep(const Geo& g, const float* src, long src_pitch, float* It, float* Gx, float* Gy,
+                             hipStream_t st);
+hipError_t launch_keyframe_prep(const Geo& g, const float* img, const float* normals, float* Is, float* cxt,
+                                float* cyt, float* X, float* X2, hipStream_t st);
+hipError_t launch_init_state(const Geo& g, float* X, float ell0, hipStream_t st);
+hipError_t launch_pf_iteration(const Geo& g, const Strengths& s, const Inputs& in, float* X, double* marg,
+                               double* M, float* var_ll, float* valid, float beta, int* health, hipStream_t st);
+hipError_t launch_fu_prologue(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* Y,
+                              int* health, hipStream_t st);
+hipError_t launch_fu_iterate(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* Y,
+                             bool final_pass, float* var_ll, float* valid, int* health, hipStream_t st);
+hipError_t launch_valid_only(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* valid,
+                             hipStream_t st);
+int stats_blocks(const Geo& g);
+hipError_t launch_frame_stats(const Geo& g, const float* X, const float* valid, int use_valid, double* partial,
+                              double* result, hipStream_t st);
+hipError_t launch_outputs(const Geo& g, const float* X, const float* var_ll, int have_var, float* inv_depth,
+                          float* inv_var, hipStream_t st);
+hipError_t launch_pack_state(const Geo& g, const float* X, float* dense, int to_dense, hipStream_t st);
+hipError_t launch_copy_plane(const Geo& g, const float* dense, float* plane, hipStream_t st);
+
+}  // namespace pv

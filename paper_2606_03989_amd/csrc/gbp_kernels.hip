@@ -1,0 +1,685 @@
+// HIP kernels of the per-pixel GBP iteration (PixVOD, arXiv 2606.03989) for
+// gfx950. One lane per pixel; FP32 structure-of-arrays state planes with a
+// padded row pitch, FP64 per-pixel algebra in registers.
+//
+// Two schedules of the same synchronous iteration (Sec. 4.1):
+//   per-factor: linearise + marginals -> messages -> belief update, one kernel
+//               each, intermediates through device memory;
+//   fused:      each pixel completes the partial messages its neighbours sent
+//               (partials do not depend on the receiver's linearisation point),
+//               updates and relinearises its variable, then linearises again
+//               and sends the next partials. One pass over the state per
+//               iteration; a prologue pass per frame starts the rotation and
+//               the last pass writes the canonical messages back.
+#include "gbp_kernels.h"
+#include "gbp_device.hpp"
+
+namespace pv {
+
+__device__ inline long pix_of(const Geo& g, int u, int v) { return (long)v * g.pitch + u; }
+
+__device__ inline bool neighbour(const Geo& g, int u, int v, int d, int& nu, int& nv) {
+    nu = u + (d == DIR_L ? -1 : (d == DIR_R ? 1 : 0));
+    nv = v + (d == DIR_U ? -1 : (d == DIR_D ? 1 : 0));
+    return nu >= 0 && nu < g.W && nv >= 0 && nv < g.H;
+}
+
+__device__ inline void load_point(const float* __restrict__ X, const Geo& g, long p, double tau[6], double& ell) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) tau[k] = (double)X[(P_TAU + k) * g.plane + p];
+    ell = (double)X[P_ELL * g.plane + p];
+}
+
+// normal-integration target and the residual seen by a receiver at pixel i
+// whose neighbour j lies in direction d; false if the edge is inactive.
+// Eq. (gbpni): r = (ell_b - ell_a) + c_a with a the left/upper pixel.
+__device__ inline bool normal_residual(const Geo& g, const Inputs& in, long pi, long pj, int d,
+                                       double ell_i, double ell_j, double& r_recv) {
+    float c;
+    double sgn;
+    if (d == DIR_L) { c = in.cxt[pj]; sgn = 1.0; }         // a = j, b = i
+    else if (d == DIR_R) { c = in.cxt[pi]; sgn = -1.0; }   // a = i, b = j
+    else if (d == DIR_U) { c = in.cyt[pj]; sgn = 1.0; }
+    else { c = in.cyt[pi]; sgn = -1.0; }
+    if (!isfinite(c)) return false;
+    // receiver's Jacobian is +1 when it is b: r_recv = (ell_b - ell_a + c) * (+1 if b)
+    r_recv = (sgn > 0.0) ? (ell_i - ell_j + (double)c) : (ell_i - ell_j - (double)c);
+    return true;
+}
+
+__device__ inline bool normal_active(const Geo& g, const Inputs& in, long pi, long pj, int d) {
+    float c = (d == DIR_L) ? in.cxt[pj] : (d == DIR_R) ? in.cxt[pi] : (d == DIR_U) ? in.cyt[pj] : in.cyt[pi];
+    return isfinite(c);
+}
+
+// B += messages (embedded: identity -> pose block, normal -> depth entry)
+__device__ inline void add_messages(double L[28], double eta[7], const float mid[4][27], const float mn[4][2]) {
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+#pragma unroll
+        for (int a = 0; a < 6; ++a) eta[a] += (double)mid[d][a];
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+            for (int c = r; c < 6; ++c) L[s7(r, c)] += (double)mid[d][6 + s6(r, c)];
+    }
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        eta[6] += (double)mn[d][0];
+        L[s7(6, 6)] += (double)mn[d][1];
+    }
+}
+
+// belief mean, relinearisation (Eq. var) and first-order transport of the
+// stored messages into the new tangent space (Sec. 4.1)
+__device__ inline bool update_and_transport(double L[28], double eta[7], double tau[6], double& ell,
+                                            float mid[4][27], float mn[4][2], double& var_ll) {
+    double idg[7];
+    const bool ok = chol7(L, idg);
+    double m[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) m[k] = eta[k];
+    chol7_solve(L, idg, m);
+    var_ll = chol7_var_last(idg);
+    double R0[9], t0[3], Rm[9], tm[3], R1[9], t1[3];
+    se3_exp(tau, R0, t0);
+    se3_exp(m, Rm, tm);
+    se3_compose(R0, t0, Rm, tm, R1, t1);
+    se3_log(R1, t1, tau);
+    ell += m[6];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+            double s = (double)mid[d][a];
+#pragma unroll
+            for (int b = 0; b < 6; ++b) s -= (double)mid[d][6 + s6(a, b)] * m[b];
+            mid[d][a] = (float)s;
+        }
+        mn[d][0] = (float)((double)mn[d][0] - (double)mn[d][1] * m[6]);
+    }
+    return ok;
+}
+
+// sender side: partial messages of pixel i towards each neighbour, from its
+// belief (L, eta) and its stored messages; written to the neighbour's slot
+__device__ inline void emit_partials(const Geo& g, const Strengths& s, const Inputs& in, int u, int v,
+                                     const double L[28], const double eta[7], const float mid[4][27],
+                                     const float mn[4][2], float* __restrict__ Y, bool& ok) {
+    double P[21], p[6], D, dv;
+    pose_marginal(L, eta, P, p);
+    ok = depth_marginal(L, eta, D, dv) && ok;
+    const long pi = pix_of(g, u, v);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        int nu, nv;
+        if (!neighbour(g, u, v, d, nu, nv)) continue;
+        const long pj = pix_of(g, nu, nv);
+        const int slot = opposite(d);
+        double V[21], vv[6], Lp[21], h[6];
+#pragma unroll
+        for (int k = 0; k < 21; ++k) V[k] = P[k] - (double)mid[d][6 + k];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) vv[k] = p[k] - (double)mid[d][k];
+        ok = identity_partial(s.lamR, V, vv, Lp, h) && ok;
+        float* dst = Y + (long)(P_MID + slot * MID_STRIDE) * g.plane + pj;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) dst[k * g.plane] = (float)h[k];
+#pragma unroll
+        for (int k = 0; k < 21; ++k) dst[(6 + k) * g.plane] = (float)Lp[k];
+        float* dn = Y + (long)(P_MN + 2 * slot) * g.plane + pj;
+        if (normal_active(g, in, pi, pj, d) && s.lamN > 0.0) {
+            double lp, hn;
+            normal_partial(s.lamN, D - (double)mn[d][1], dv - (double)mn[d][0], lp, hn);
+            dn[0] = (float)hn;
+            dn[g.plane] = (float)lp;
+        } else {
+            dn[0] = 0.0f;
+            dn[g.plane] = 0.0f;
+        }
+    }
+}
+
+// adds one completed message (identity eta/Lambda, normal eta/lambda) of slot
+// d to the belief in FP64 and keeps its FP32 storage copy
+__device__ inline void accumulate_message(double L[28], double eta[7], const double id_eta[6], const float id_lam[21],
+                                          double n_eta, float n_lam, float mid_d[27], float mn_d[2]) {
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+        eta[a] += id_eta[a];
+        mid_d[a] = (float)id_eta[a];
+    }
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+        for (int c = r; c < 6; ++c) L[s7(r, c)] += (double)id_lam[s6(r, c)];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) mid_d[6 + k] = id_lam[k];
+    eta[6] += n_eta;
+    L[s7(6, 6)] += (double)n_lam;
+    mn_d[0] = (float)n_eta;
+    mn_d[1] = n_lam;
+}
+
+// receiver side: completes the partial in slot d with the residual at both
+// linearisation points, eta = h - Lambda' r, and adds it to the belief
+__device__ inline void complete_partials(const Geo& g, const Strengths& s, const Inputs& in,
+                                         const float* __restrict__ X, int u, int v, const double R[9],
+                                         const double t[3], double ell, double L[28], double eta[7],
+                                         float mid[4][27], float mn[4][2]) {
+    const long pi = pix_of(g, u, v);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        int nu, nv;
+        if (!neighbour(g, u, v, d, nu, nv)) {
+#pragma unroll
+            for (int k = 0; k < 27; ++k) mid[d][k] = 0.0f;
+            mn[d][0] = mn[d][1] = 0.0f;
+            continue;
+        }
+        const long pj = pix_of(g, nu, nv);
+        double tj[6], ellj, Rj[9], trj[3], r[6];
+        load_point(X, g, pj, tj, ellj);
+        se3_exp(tj, Rj, trj);
+        se3_between(Rj, trj, R, t, r);
+        const float* src = X + (long)(P_MID + d * MID_STRIDE) * g.plane + pi;
+        float part[27];
+#pragma unroll
+        for (int k = 0; k < 27; ++k) part[k] = src[k * g.plane];
+        double e6[6];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+            double e = (double)part[a];
+#pragma unroll
+            for (int b = 0; b < 6; ++b) e -= (double)part[6 + s6(a, b)] * r[b];
+            e6[a] = e;
+        }
+        double ne = 0.0;
+        float nl = 0.0f;
+        double rn;
+        if (s.lamN > 0.0 && normal_residual(g, in, pi, pj, d, ell, ellj, rn)) {
+            const float* sn = X + (long)(P_MN + 2 * d) * g.plane + pi;
+            nl = sn[g.plane];
+            ne = (double)sn[0] - (double)nl * rn;
+        }
+        accumulate_message(L, eta, e6, part + 6, ne, nl, mid[d], mn[d]);
+    }
+}
+
+__device__ inline void store_point(float* __restrict__ Y, const Geo& g, long p, const double tau[6], double ell) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Y[(P_TAU + k) * g.plane + p] = (float)tau[k];
+    Y[P_ELL * g.plane + p] = (float)ell;
+}
+
+__device__ inline void store_messages(float* __restrict__ Y, const Geo& g, long p, const float mid[4][27],
+                                      const float mn[4][2]) {
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+#pragma unroll
+        for (int k = 0; k < 27; ++k) Y[(long)(P_MID + d * MID_STRIDE + k) * g.plane + p] = mid[d][k];
+        Y[(long)(P_MN + 2 * d) * g.plane + p] = mn[d][0];
+        Y[(long)(P_MN + 2 * d + 1) * g.plane + p] = mn[d][1];
+    }
+}
+
+__device__ inline void load_messages(const float* __restrict__ X, const Geo& g, long p, float mid[4][27],
+                                     float mn[4][2]) {
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+#pragma unroll
+        for (int k = 0; k < 27; ++k) mid[d][k] = X[(long)(P_MID + d * MID_STRIDE + k) * g.plane + p];
+        mn[d][0] = X[(long)(P_MN + 2 * d) * g.plane + p];
+        mn[d][1] = X[(long)(P_MN + 2 * d + 1) * g.plane + p];
+    }
+}
+
+// rounds a double point to the stored FP32 precision
+__device__ inline void round_point(double tau[6], double& ell) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) tau[k] = (double)(float)tau[k];
+    ell = (double)(float)ell;
+}
+
+// ---------------------------------------------------------------------------
+// frame and keyframe preparation
+
+// central differences inside, one-sided at the border (row a1)
+__global__ void k_frame_prep(Geo g, const float* __restrict__ src, long src_pitch, float* __restrict__ It,
+                             float* __restrict__ Gx, float* __restrict__ Gy) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y * blockDim.y + threadIdx.y;
+    if (u >= g.W || v >= g.H) return;
+    const float* row = src + (long)v * src_pitch;
+    const float c = row[u];
+    float gx, gy;
+    if (u == 0) gx = row[1] - row[0];
+    else if (u == g.W - 1) gx = row[u] - row[u - 1];
+    else gx = 0.5f * (row[u + 1] - row[u - 1]);
+    if (v == 0) gy = src[src_pitch + u] - row[u];
+    else if (v == g.H - 1) gy = row[u] - src[(long)(v - 1) * src_pitch + u];
+    else gy = 0.5f * (src[(long)(v + 1) * src_pitch + u] - src[(long)(v - 1) * src_pitch + u]);
+    const long p = pix_of(g, u, v);
+    It[p] = c;
+    Gx[p] = gx;
+    Gy[p] = gy;
+}
+
+// keyframe image, normal-integration targets (row a2) and the state reset:
+// pose linearisation points to identity, messages to zero, log-depth kept
+__global__ void k_keyframe_prep(Geo g, const float* __restrict__ img, const float* __restrict__ normals,
+                                float* __restrict__ Is, float* __restrict__ cxt, float* __restrict__ cyt,
+                                float* __restrict__ X, float* __restrict__ X2) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y * blockDim.y + threadIdx.y;
+    if (u >= g.W || v >= g.H) return;
+    const long dense = (long)v * g.W + u;
+    const long p = pix_of(g, u, v);
+    Is[p] = img[dense];
+    const double q0 = ((double)u - g.cx) / g.fx, q1 = ((double)v - g.cy) / g.fy;
+    const double n0 = normals[3 * dense], n1 = normals[3 * dense + 1], n2 = normals[3 * dense + 2];
+    const double nq = n0 * q0 + n1 * q1 + n2;
+    const double qn = sqrt(q0 * q0 + q1 * q1 + 1.0);
+    const bool ok = isfinite(nq) && fabs(nq) >= 1e-3 * qn;
+    cxt[p] = ok ? (float)(n0 / (g.fx * nq)) : __int_as_float(0x7fc00000);
+    cyt[p] = ok ? (float)(n1 / (g.fy * nq)) : __int_as_float(0x7fc00000);
+    const float ell = X[P_ELL * g.plane + p];
+    for (int k = 0; k < N_PLANES; ++k) {
+        X[(long)k * g.plane + p] = 0.0f;
+        X2[(long)k * g.plane + p] = 0.0f;
+    }
+    X[P_ELL * g.plane + p] = ell;
+    X2[P_ELL * g.plane + p] = ell;
+}
+
+__global__ void k_init_state(Geo g, float* __restrict__ X, float ell0) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y * blockDim.y + threadIdx.y;
+    if (u >= g.W || v >= g.H) return;
+    const long p = pix_of(g, u, v);
+    for (int k = 0; k < N_PLANES; ++k) X[(long)k * g.plane + p] = 0.0f;
+    X[P_ELL * g.plane + p] = ell0;
+}
+
+// ---------------------------------------------------------------------------
+// per-factor schedule
+
+// L + B + V: unary factors, belief, pose and depth marginals (FP64 scratch,
+// 29 planes: P packed 21, p 6, D, dv)
+__global__ __launch_bounds__(256) void k_pf_linearise(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
+                                                      double* __restrict__ marg, float* __restrict__ valid,
+                                                      int* __restrict__ health) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y * blockDim.y + threadIdx.y;
+    if (u >= g.W || v >= g.H) return;
+    const long p = pix_of(g, u, v);
+    double tau[6], ell, R[9], t[3], L[28], eta[7];
+    load_point(X, g, p, tau, ell);
+    se3_exp(tau, R, t);
+    const bool val = unary_factors(g, s, in, u, v, tau, R, t, ell, L, eta);
+    float mid[4][27], mn[4][2];
+    load_messages(X, g, p, mid, mn);
+    add_messages(L, eta, mid, mn);
+    double P[21], pv_[6], D, dv;
+    pose_marginal(L, eta, P, pv_);
+    const bool ok = depth_marginal(L, eta, D, dv);
+#pragma unroll
+    for (int k = 0; k < 21; ++k) marg[(long)k * g.plane + p] = P[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) marg[(long)(21 + k) * g.plane + p] = pv_[k];
+    marg[(long)27 * g.plane + p] = D;
+    marg[(long)28 * g.plane + p] = dv;
+    valid[p] = val ? 1.0f : 0.0f;
+    if (!ok) atomicOr(health, 1);
+}
+
+// F: every pixel computes its four incoming messages from its neighbours'
+// marginals and the messages those neighbours hold from the shared factor.
+// Output (FP64 scratch, 29 planes per direction): identity eta(6), identity
+// Lambda(21, already at storage precision), normal eta, normal lambda.
+__global__ __launch_bounds__(256) void k_pf_messages(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
+                                                     const double* __restrict__ marg, double* __restrict__ M,
+                                                     float beta, int* __restrict__ health) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y * blockDim.y + threadIdx.y;
+    if (u >= g.W || v >= g.H) return;
+    const long pi = pix_of(g, u, v);
+    double tau[6], ell, R[9], t[3];
+    load_point(X, g, pi, tau, ell);
+    se3_exp(tau, R, t);
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        double out[29];
+#pragma unroll
+        for (int k = 0; k < 29; ++k) out[k] = 0.0;
+        int nu, nv;
+        if (neighbour(g, u, v, d, nu, nv)) {
+            const long pj = pix_of(g, nu, nv);
+            const int slot = opposite(d);
+            double V[21], vv[6], Lp[21], h[6];
+#pragma unroll
+            for (int k = 0; k < 21; ++k)
+                V[k] = marg[(long)k * g.plane + pj] - (double)X[(long)(P_MID + slot * MID_STRIDE + 6 + k) * g.plane + pj];
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                vv[k] = marg[(long)(21 + k) * g.plane + pj] - (double)X[(long)(P_MID + slot * MID_STRIDE + k) * g.plane + pj];
+            ok = identity_partial(s.lamR, V, vv, Lp, h) && ok;
+            // the partial is rounded to storage precision as in the fused schedule
+            float part[27];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) part[k] = (float)h[k];
+#pragma unroll
+            for (int k = 0; k < 21; ++k) part[6 + k] = (float)Lp[k];
+            double tj[6], ellj, Rj[9], trj[3], r[6];
+            load_point(X, g, pj, tj, ellj);
+            se3_exp(tj, Rj, trj);
+            se3_between(Rj, trj, R, t, r);
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {
+                double e = (double)part[a];
+#pragma unroll
+                for (int b = 0; b < 6; ++b) e -= (double)part[6 + s6(a, b)] * r[b];
+                out[a] = e;
+            }
+#pragma unroll
+            for (int k = 0; k < 21; ++k) out[6 + k] = (double)part[6 + k];
+            double rn;
+            if (s.lamN > 0.0 && normal_residual(g, in, pi, pj, d, ell, ellj, rn)) {
+                const double ls = marg[(long)27 * g.plane + pj] - (double)X[(long)(P_MN + 2 * slot + 1) * g.plane + pj];
+                const double vs = marg[(long)28 * g.plane + pj] - (double)X[(long)(P_MN + 2 * slot) * g.plane + pj];
+                double lp, hn;
+                normal_partial(s.lamN, ls, vs, lp, hn);
+                const float fl = (float)lp, fh = (float)hn;
+                out[27] = (double)fh - (double)fl * rn;
+                out[28] = (double)fl;
+            }
+            if (beta != 0.0f) {
+                // damping towards the stored message; the blended Lambda is
+                // rounded to storage precision like every stored Lambda
+                const double b = beta, a = 1.0 - b;
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+                    out[k] = a * out[k] + b * X[(long)(P_MID + d * MID_STRIDE + k) * g.plane + pi];
+#pragma unroll
+                for (int k = 6; k < 27; ++k)
+                    out[k] = (double)(float)(a * out[k] + b * X[(long)(P_MID + d * MID_STRIDE + k) * g.plane + pi]);
+                out[27] = a * out[27] + b * X[(long)(P_MN + 2 * d) * g.plane + pi];
+                out[28] = (double)(float)(a * out[28] + b * X[(long)(P_MN + 2 * d + 1) * g.plane + pi]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 29; ++k) M[(long)(d * 29 + k) * g.plane + pi] = out[k];
+    }
+    if (!ok) atomicOr(health, 1);
+}
+
+// U: new belief from the recomputed unary and the new messages, relinearise,
+// transport, write the state in place
+__global__ __launch_bounds__(256) void k_pf_update(Geo g, Strengths s, Inputs in, float* __restrict__ X,
+                                                   const double* __restrict__ M, float* __restrict__ var_ll,
+                                                   float* __restrict__ valid, int* __restrict__ health) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y * blockDim.y + threadIdx.y;
+    if (u >= g.W || v >= g.H) return;
+    const long p = pix_of(g, u, v);
+    double tau[6], ell, R[9], t[3], L[28], eta[7];
+    load_point(X, g, p, tau, ell);
+    se3_exp(tau, R, t);
+    const bool val = unary_factors(g, s, in, u, v, tau, R, t, ell, L, eta);
+    float mid[4][27], mn[4][2];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        double e6[6];
+        float lam[21];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) e6[k] = M[(long)(d * 29 + k) * g.plane + p];
+#pragma unroll
+        for (int k = 0; k < 21; ++k) lam[k] = (float)M[(long)(d * 29 + 6 + k) * g.plane + p];
+        const double ne = M[(long)(d * 29 + 27) * g.plane + p];
+        const float nl = (float)M[(long)(d * 29 + 28) * g.plane + p];
+        accumulate_message(L, eta, e6, lam, ne, nl, mid[d], mn[d]);
+    }
+    double var;
+    const bool ok = update_and_transport(L, eta, tau, ell, mid, mn, var);
+    round_point(tau, ell);
+    store_point(X, g, p, tau, ell);
+    store_messages(X, g, p, mid, mn);
+    var_ll[p] = (float)var;
+    valid[p] = val ? 1.0f : 0.0f;
+    if (!ok) atomicOr(health, 1);
+}
+
+// ---------------------------------------------------------------------------
+// fused schedule
+
+// prologue: belief of the canonical state and the first partials
+__global__ __launch_bounds__(256) void k_fu_prologue(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
+                                                     float* __restrict__ Y, int* __restrict__ health) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y * blockDim.y + threadIdx.y;
+    if (u >= g.W || v >= g.H) return;
+    const long p = pix_of(g, u, v);
+    double tau[6], ell, R[9], t[3], L[28], eta[7];
+    load_point(X, g, p, tau, ell);
+    se3_exp(tau, R, t);
+    unary_factors(g, s, in, u, v, tau, R, t, ell, L, eta);
+    float mid[4][27], mn[4][2];
+    load_messages(X, g, p, mid, mn);
+    add_messages(L, eta, mid, mn);
+    bool ok = true;
+    emit_partials(g, s, in, u, v, L, eta, mid, mn, Y, ok);
+    store_point(Y, g, p, tau, ell);
+    if (!ok) atomicOr(health, 1);
+}
+
+// one iteration: complete, update, relinearise, then (not FINAL) emit the
+// next partials or (FINAL) write the canonical state and per-pixel outputs
+template <bool FINAL>
+__global__ __launch_bounds__(256) void k_fu_iterate(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
+                                                    float* __restrict__ Y, float* __restrict__ var_ll,
+                                                    float* __restrict__ valid, int* __restrict__ health) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y * blockDim.y + threadIdx.y;
+    if (u >= g.W || v >= g.H) return;
+    const long p = pix_of(g, u, v);
+    double tau[6], ell, R[9], t[3], L[28], eta[7];
+    load_point(X, g, p, tau, ell);
+    se3_exp(tau, R, t);
+    const bool val = unary_factors(g, s, in, u, v, tau, R, t, ell, L, eta);
+    float mid[4][27], mn[4][2];
+    complete_partials(g, s, in, X, u, v, R, t, ell, L, eta, mid, mn);
+    double var;
+    bool ok = update_and_transport(L, eta, tau, ell, mid, mn, var);
+    round_point(tau, ell);
+    store_point(Y, g, p, tau, ell);
+    if (FINAL) {
+        store_messages(Y, g, p, mid, mn);
+        var_ll[p] = (float)var;
+        valid[p] = val ? 1.0f : 0.0f;
+    } else {
+        se3_exp(tau, R, t);
+        unary_factors(g, s, in, u, v, tau, R, t, ell, L, eta);
+        add_messages(L, eta, mid, mn);
+        emit_partials(g, s, in, u, v, L, eta, mid, mn, Y, ok);
+    }
+    if (!ok) atomicOr(health, 1);
+}
+
+// ---------------------------------------------------------------------------
+// per-frame statistics (rows a10-a12), deterministic two-stage reduction
+
+constexpr int RED_THREADS = 256;
+
+// per block: sum of the six pose planes, valid count, non-finite count
+__global__ __launch_bounds__(RED_THREADS) void k_frame_stats(Geo g, const float* __restrict__ X,
+                                                            const float* __restrict__ valid, int use_valid,
+                                                            double* __restrict__ partial) {
+    __shared__ double sh[8][RED_THREADS];
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const long N = (long)g.H * g.W;
+    for (long i = (long)blockIdx.x * RED_THREADS + threadIdx.x; i < N; i += (long)gridDim.x * RED_THREADS) {
+        const int u = (int)(i % g.W), v = (int)(i / g.W);
+        const long p = pix_of(g, u, v);
+        bool fin = true;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const float x = X[(long)k * g.plane + p];
+            acc[k] += (double)x;
+            fin = fin && isfinite(x);
+        }
+        fin = fin && isfinite(X[(long)P_ELL * g.plane + p]);
+        acc[6] += use_valid ? (double)valid[p] : 0.0;
+        acc[7] += fin ? 0.0 : 1.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sh[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 8) partial[(long)blockIdx.x * 8 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void k_frame_final(int nblocks, const double* __restrict__ partial, double* __restrict__ result) {
+    const int k = threadIdx.x;
+    if (k >= 8) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += partial[(long)b * 8 + k];
+    result[k] = s;
+}
+
+// output maps: inverse depth and its delta-method variance (dense H x W)
+__global__ void k_outputs(Geo g, const float* __restrict__ X, const float* __restrict__ var_ll, int have_var,
+                          float* __restrict__ inv_depth, float* __restrict__ inv_var) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y * blockDim.y + threadIdx.y;
+    if (u >= g.W || v >= g.H) return;
+    const long p = pix_of(g, u, v);
+    const double rho = exp(-(double)X[(long)P_ELL * g.plane + p]);
+    const long o = (long)v * g.W + u;
+    if (inv_depth) inv_depth[o] = (float)rho;
+    if (inv_var) inv_var[o] = have_var ? (float)(rho * rho * (double)var_ll[p]) : __int_as_float(0x7fc00000);
+}
+
+// valid-warp flags of the current state without iterating (n_iters == 0)
+__global__ __launch_bounds__(256) void k_valid_only(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
+                                                    float* __restrict__ valid) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y * blockDim.y + threadIdx.y;
+    if (u >= g.W || v >= g.H) return;
+    const long p = pix_of(g, u, v);
+    double tau[6], ell, R[9], t[3], L[28], eta[7];
+    load_point(X, g, p, tau, ell);
+    se3_exp(tau, R, t);
+    valid[p] = unary_factors(g, s, in, u, v, tau, R, t, ell, L, eta) ? 1.0f : 0.0f;
+}
+
+// state exchange: pitched planes <-> dense planes
+__global__ void k_pack_state(Geo g, const float* __restrict__ X, float* __restrict__ dense, int to_dense) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y * blockDim.y + threadIdx.y;
+    if (u >= g.W || v >= g.H) return;
+    const long p = pix_of(g, u, v);
+    const long N = (long)g.H * g.W, o = (long)v * g.W + u;
+    for (int k = 0; k < N_PLANES; ++k) {
+        if (to_dense) dense[(long)k * N + o] = X[(long)k * g.plane + p];
+        else ((float*)X)[(long)k * g.plane + p] = dense[(long)k * N + o];
+    }
+}
+
+__global__ void k_copy_plane(Geo g, const float* __restrict__ dense, float* __restrict__ plane) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y * blockDim.y + threadIdx.y;
+    if (u >= g.W || v >= g.H) return;
+    plane[pix_of(g, u, v)] = dense[(long)v * g.W + u];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+static dim3 grid2d(const Geo& g, dim3 b) { return dim3((g.W + b.x - 1) / b.x, (g.H + b.y - 1) / b.y); }
+static const dim3 kBlock(64, 4);
+
+hipError_t launch_frame_prep(const Geo& g, const float* src, long src_pitch, float* It, float* Gx, float* Gy,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_frame_prep, grid2d(g, kBlock), kBlock, 0, st, g, src, src_pitch, It, Gx, Gy);
+    return hipGetLastError();
+}
+
+hipError_t launch_keyframe_prep(const Geo& g, const float* img, const float* normals, float* Is, float* cxt,
+                                float* cyt, float* X, float* X2, hipStream_t st) {
+    hipLaunchKernelGGL(k_keyframe_prep, grid2d(g, kBlock), kBlock, 0, st, g, img, normals, Is, cxt, cyt, X, X2);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_state(const Geo& g, float* X, float ell0, hipStream_t st) {
+    hipLaunchKernelGGL(k_init_state, grid2d(g, kBlock), kBlock, 0, st, g, X, ell0);
+    return hipGetLastError();
+}
+
+hipError_t launch_pf_iteration(const Geo& g, const Strengths& s, const Inputs& in, float* X, double* marg,
+                               double* M, float* var_ll, float* valid, float beta, int* health, hipStream_t st) {
+    hipLaunchKernelGGL(k_pf_linearise, grid2d(g, kBlock), kBlock, 0, st, g, s, in, X, marg, valid, health);
+    hipLaunchKernelGGL(k_pf_messages, grid2d(g, kBlock), kBlock, 0, st, g, s, in, X, marg, M, beta, health);
+    hipLaunchKernelGGL(k_pf_update, grid2d(g, kBlock), kBlock, 0, st, g, s, in, X, M, var_ll, valid, health);
+    return hipGetLastError();
+}
+
+hipError_t launch_fu_prologue(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* Y,
+                              int* health, hipStream_t st) {
+    hipLaunchKernelGGL(k_fu_prologue, grid2d(g, kBlock), kBlock, 0, st, g, s, in, X, Y, health);
+    return hipGetLastError();
+}
+
+hipError_t launch_fu_iterate(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* Y,
+                             bool final_pass, float* var_ll, float* valid, int* health, hipStream_t st) {
+    if (final_pass)
+        hipLaunchKernelGGL(k_fu_iterate<true>, grid2d(g, kBlock), kBlock, 0, st, g, s, in, X, Y, var_ll, valid, health);
+    else
+        hipLaunchKernelGGL(k_fu_iterate<false>, grid2d(g, kBlock), kBlock, 0, st, g, s, in, X, Y, var_ll, valid, health);
+    return hipGetLastError();
+}
+
+hipError_t launch_valid_only(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* valid,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_valid_only, grid2d(g, kBlock), kBlock, 0, st, g, s, in, X, valid);
+    return hipGetLastError();
+}
+
+int stats_blocks(const Geo& g) {
+    const long N = (long)g.H * g.W;
+    long b = (N + RED_THREADS * 8 - 1) / (RED_THREADS * 8);
+    if (b < 1) b = 1;
+    if (b > 1024) b = 1024;
+    return (int)b;
+}
+
+hipError_t launch_frame_stats(const Geo& g, const float* X, const float* valid, int use_valid, double* partial,
+                              double* result, hipStream_t st) {
+    const int nb = stats_blocks(g);
+    hipLaunchKernelGGL(k_frame_stats, dim3(nb), dim3(RED_THREADS), 0, st, g, X, valid, use_valid, partial);
+    hipLaunchKernelGGL(k_frame_final, dim3(1), dim3(64), 0, st, nb, partial, result);
+    return hipGetLastError();
+}
+
+hipError_t launch_outputs(const Geo& g, const float* X, const float* var_ll, int have_var, float* inv_depth,
+                          float* inv_var, hipStream_t st) {
+    hipLaunchKernelGGL(k_outputs, grid2d(g, kBlock), kBlock, 0, st, g, X, var_ll, have_var, inv_depth, inv_var);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_state(const Geo& g, const float* X, float* dense, int to_dense, hipStream_t st) {
+    hipLaunchKernelGGL(k_pack_state, grid2d(g, kBlock), kBlock, 0, st, g, X, dense, to_dense);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_plane(const Geo& g, const float* dense, float* plane, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy_plane, grid2d(g, kBlock), kBlock, 0, st, g, dense, plane);
+    return hipGetLastError();
+}
+
+}  // namespace pv

@@ -1,0 +1,635 @@
+// Host runtime and C-ABI of libpixvod (declarations in include/pixvod.h).
+//
+// A context owns the FP32 state planes (two ping-pong copies of 123 planes,
+// row pitch padded to 64 floats), the keyframe/frame input planes and the
+// reduction buffers of one image sequence on one device, and drives the
+// iteration schedules on a caller-selected HIP stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pixvod.h"
+#include "gbp_device.hpp"
+#include "gbp_kernels.h"
+
+using namespace pv;
+
+static thread_local std::string g_last_error;
+
+struct pixvod_ctx {
+    int H = 0, W = 0, pitch = 0;
+    long plane = 0;
+    pixvod_intrinsics K{};
+    pixvod_params P{};
+    int device = 0;
+    hipStream_t own_stream = nullptr, stream = nullptr;
+    int schedule = PIXVOD_SCHED_FUSED;
+    float* X[2] = {nullptr, nullptr};
+    int cur = 0;
+    float *Is = nullptr, *cxt = nullptr, *cyt = nullptr, *sig = nullptr;
+    float *It = nullptr, *Gx = nullptr, *Gy = nullptr;
+    float *var_ll = nullptr, *valid = nullptr;
+    float *frame_stage = nullptr, *kf_stage = nullptr, *out_stage = nullptr;
+    float* dense_state = nullptr;
+    double* marg = nullptr;
+    double* msg = nullptr;
+    double *partial = nullptr, *result = nullptr;
+    int* health = nullptr;
+    double* h_result = nullptr;
+    int* h_health = nullptr;
+    bool have_kf = false, have_frame = false, has_sigma = false, have_track = false, have_var = false;
+    double T_w_kf[16];
+    double xi_last[6];
+    int frames_since_kf = 0;
+    std::string err;
+    // kernel timing
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    struct Pending { hipEvent_t a, b; int kind; };
+    std::vector<Pending> pending;
+    double prof_ms[PIXVOD_PROF_KINDS] = {0, 0, 0, 0};
+    int64_t prof_n[PIXVOD_PROF_KINDS] = {0, 0, 0, 0};
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+
+static int fail(pixvod_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                   \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((ctx), PIXVOD_EHIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+static void host_se3_exp(const double xi[6], double T[16]) {
+    const double* w = xi;
+    const double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    double A, B, C;
+    if (th2 < 1e-2) {
+        const double t4 = th2 * th2, t6 = t4 * th2, t8 = t4 * t4;
+        A = 1.0 - th2 / 6.0 + t4 / 120.0 - t6 / 5040.0 + t8 / 362880.0;
+        B = 0.5 - th2 / 24.0 + t4 / 720.0 - t6 / 40320.0 + t8 / 3628800.0;
+        C = 1.0 / 6.0 - th2 / 120.0 + t4 / 5040.0 - t6 / 362880.0 + t8 / 39916800.0;
+    } else {
+        const double th = std::sqrt(th2), sh = std::sin(0.5 * th);
+        A = std::sin(th) / th;
+        B = 2.0 * sh * sh / th2;
+        C = (th - std::sin(th)) / (th2 * th);
+    }
+    const double Wm[9] = {0, -w[2], w[1], w[2], 0, -w[0], -w[1], w[0], 0};
+    const double W2[9] = {w[0] * w[0] - th2, w[0] * w[1], w[0] * w[2], w[1] * w[0], w[1] * w[1] - th2,
+                          w[1] * w[2], w[2] * w[0], w[2] * w[1], w[2] * w[2] - th2};
+    std::memset(T, 0, 16 * sizeof(double));
+    for (int r = 0; r < 3; ++r) {
+        double tr = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const double I = (r == c) ? 1.0 : 0.0;
+            T[r * 4 + c] = I + A * Wm[r * 3 + c] + B * W2[r * 3 + c];
+            tr += (I + B * Wm[r * 3 + c] + C * W2[r * 3 + c]) * xi[3 + c];
+        }
+        T[r * 4 + 3] = tr;
+    }
+    T[15] = 1.0;
+}
+
+static void host_se3_inverse(const double T[16], double Ti[16]) {
+    std::memset(Ti, 0, 16 * sizeof(double));
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) Ti[r * 4 + c] = T[c * 4 + r];
+    for (int r = 0; r < 3; ++r)
+        Ti[r * 4 + 3] = -(Ti[r * 4] * T[3] + Ti[r * 4 + 1] * T[7] + Ti[r * 4 + 2] * T[11]);
+    Ti[15] = 1.0;
+}
+
+static void host_mat4_mul(const double A[16], const double B[16], double C[16]) {
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < 4; ++k) s += A[r * 4 + k] * B[k * 4 + c];
+            C[r * 4 + c] = s;
+        }
+}
+
+static Geo geo_of(const pixvod_ctx* c) {
+    Geo g;
+    g.H = c->H;
+    g.W = c->W;
+    g.pitch = c->pitch;
+    g.plane = c->plane;
+    g.fx = c->K.fx;
+    g.fy = c->K.fy;
+    g.cx = c->K.cx;
+    g.cy = c->K.cy;
+    return g;
+}
+
+static double inv_sq(float s) {
+    if (std::isinf(s)) return 0.0;
+    return 1.0 / ((double)s * (double)s);
+}
+
+static Strengths strengths_of(const pixvod_ctx* c) {
+    Strengths s;
+    std::memset(&s, 0, sizeof(s));
+    s.lamP = inv_sq(c->P.sigma_P);
+    s.lamR = inv_sq(c->P.sigma_R);
+    s.lamN = inv_sq(c->P.sigma_N);
+    s.lamD = inv_sq(c->P.sigma_D);
+    s.huber_k = c->P.huber_k;
+    s.prior_ell = c->P.prior_log_depth;
+    bool ident = true;
+    double xi[6];
+    for (int k = 0; k < 6; ++k) {
+        xi[k] = c->P.prior_xi[k];
+        ident = ident && (xi[k] == 0.0);
+    }
+    double T[16], Ti[16];
+    host_se3_exp(xi, T);
+    host_se3_inverse(T, Ti);
+    for (int r = 0; r < 3; ++r) {
+        for (int cc = 0; cc < 3; ++cc) s.prior_R[r * 3 + cc] = Ti[r * 4 + cc];
+        s.prior_t[r] = Ti[r * 4 + 3];
+    }
+    s.prior_is_identity = ident ? 1 : 0;
+    s.has_sigma_map = c->has_sigma ? 1 : 0;
+    return s;
+}
+
+static Inputs inputs_of(const pixvod_ctx* c) {
+    Inputs in;
+    in.Is = c->Is;
+    in.cxt = c->cxt;
+    in.cyt = c->cyt;
+    in.sigD = c->sig;
+    in.It = c->It;
+    in.Gx = c->Gx;
+    in.Gy = c->Gy;
+    return in;
+}
+
+static bool finite_params(const pixvod_params* p) {
+    const float v[] = {p->sigma_D, p->sigma_P, p->huber_k, p->init_inv_depth, p->prior_log_depth,
+                       p->kf_min_valid_frac, p->damping};
+    for (float x : v)
+        if (!std::isfinite(x)) return false;
+    for (int k = 0; k < 6; ++k)
+        if (!std::isfinite(p->prior_xi[k])) return false;
+    return p->sigma_D > 0 && p->sigma_P > 0 && p->sigma_R > 0 && p->sigma_N > 0 && p->huber_k > 0 &&
+           p->init_inv_depth > 0 && p->damping >= 0 && p->damping < 1 && p->kf_max_frames >= 1;
+}
+
+template <typename T>
+static int dev_alloc(pixvod_ctx* c, T** p, size_t n) {
+    if (hipMalloc((void**)p, n * sizeof(T)) != hipSuccess) {
+        *p = nullptr;
+        return fail(c, PIXVOD_ENOMEM, "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
+    }
+    return PIXVOD_OK;
+}
+
+static hipEvent_t take_event(pixvod_ctx* c) {
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// records the start event of a timed launch (nullptr when not profiling)
+static hipEvent_t prof_begin(pixvod_ctx* c) {
+    if (!c->prof) return nullptr;
+    hipEvent_t a = take_event(c);
+    if (a) (void)hipEventRecord(a, c->stream);
+    return a;
+}
+
+static void prof_end(pixvod_ctx* c, hipEvent_t a, int kind) {
+    if (!a) return;
+    hipEvent_t b = take_event(c);
+    if (!b) {
+        c->ev_pool.push_back(a);
+        return;
+    }
+    (void)hipEventRecord(b, c->stream);
+    c->pending.push_back({a, b, kind});
+}
+
+// folds completed event pairs into the per-kind totals (stream must be idle)
+static void prof_collect(pixvod_ctx* c) {
+    for (auto& p : c->pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            c->prof_ms[p.kind] += ms;
+            c->prof_n[p.kind] += 1;
+        }
+        c->ev_pool.push_back(p.a);
+        c->ev_pool.push_back(p.b);
+    }
+    c->pending.clear();
+}
+
+static void release(pixvod_ctx* c) {
+    void* bufs[] = {c->X[0], c->X[1], c->Is, c->cxt, c->cyt, c->sig, c->It, c->Gx, c->Gy, c->var_ll,
+                    c->valid, c->frame_stage, c->kf_stage, c->out_stage, c->dense_state, c->marg, c->msg,
+                    c->partial, c->result, c->health};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    if (c->h_result) (void)hipHostFree(c->h_result);
+    if (c->h_health) (void)hipHostFree(c->h_health);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+    for (auto& p : c->pending) {
+        c->ev_pool.push_back(p.a);
+        c->ev_pool.push_back(p.b);
+    }
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+}
+
+// ---------------------------------------------------------------------------
+// the ABI
+
+extern "C" {
+
+void pixvod_default_params(pixvod_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->sigma_D = 5e-3f;
+    p->sigma_P = 1.0f;
+    p->sigma_R = 4e-4f;
+    p->sigma_N = 1e-3f;
+    p->huber_k = 400.0f;
+    p->init_inv_depth = 1.0f;
+    p->prior_log_depth = 0.0f;
+    p->kf_max_frames = 150;
+    p->kf_min_valid_frac = 0.5f;
+    p->damping = 0.0f;
+}
+
+const char* pixvod_version(void) { return "pixvod 0.1.0 (gfx950)"; }
+
+const char* pixvod_last_error(const pixvod_ctx* c) { return c ? c->err.c_str() : g_last_error.c_str(); }
+
+int pixvod_create(int H, int W, const pixvod_intrinsics* K, const pixvod_params* params, pixvod_ctx** out) {
+    if (!out) return fail(nullptr, PIXVOD_EINVAL, "out_ctx is NULL");
+    *out = nullptr;
+    if (H < 2 || W < 2) return fail(nullptr, PIXVOD_EINVAL, "H and W must be >= 2");
+    if ((long)H * (long)W > (1L << 28)) return fail(nullptr, PIXVOD_EINVAL, "image too large");
+    if (!K || !(K->fx > 0) || !(K->fy > 0) || !std::isfinite(K->cx) || !std::isfinite(K->cy))
+        return fail(nullptr, PIXVOD_EINVAL, "intrinsics must be finite with fx, fy > 0");
+    pixvod_params P;
+    if (params) P = *params;
+    else pixvod_default_params(&P);
+    if (!finite_params(&P)) return fail(nullptr, PIXVOD_EINVAL, "invalid parameters");
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+        return fail(nullptr, PIXVOD_ENODEV, "no HIP device available");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(nullptr, PIXVOD_ENODEV, "hipGetDevice failed");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return fail(nullptr, PIXVOD_ENODEV, "hipGetDeviceProperties failed");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(nullptr, PIXVOD_ENODEV, std::string("device is ") + prop.gcnArchName + ", need gfx950");
+
+    pixvod_ctx* c = new pixvod_ctx();
+    c->H = H;
+    c->W = W;
+    c->pitch = (W + 63) / 64 * 64;
+    c->plane = (long)H * c->pitch;
+    c->K = *K;
+    c->P = P;
+    c->device = dev;
+    c->schedule = (P.damping != 0.0f) ? PIXVOD_SCHED_PER_FACTOR : PIXVOD_SCHED_FUSED;
+    std::memset(c->T_w_kf, 0, sizeof(c->T_w_kf));
+    for (int k = 0; k < 4; ++k) c->T_w_kf[k * 5] = 1.0;
+    std::memset(c->xi_last, 0, sizeof(c->xi_last));
+    int rc = PIXVOD_OK;
+    const size_t pl = (size_t)c->plane, N = (size_t)H * W;
+    const int nb = stats_blocks(geo_of(c));
+    if (!rc) rc = dev_alloc(c, &c->X[0], pl * N_PLANES);
+    if (!rc) rc = dev_alloc(c, &c->X[1], pl * N_PLANES);
+    if (!rc) rc = dev_alloc(c, &c->Is, pl);
+    if (!rc) rc = dev_alloc(c, &c->cxt, pl);
+    if (!rc) rc = dev_alloc(c, &c->cyt, pl);
+    if (!rc) rc = dev_alloc(c, &c->sig, pl);
+    if (!rc) rc = dev_alloc(c, &c->It, pl);
+    if (!rc) rc = dev_alloc(c, &c->Gx, pl);
+    if (!rc) rc = dev_alloc(c, &c->Gy, pl);
+    if (!rc) rc = dev_alloc(c, &c->var_ll, pl);
+    if (!rc) rc = dev_alloc(c, &c->valid, pl);
+    if (!rc) rc = dev_alloc(c, &c->frame_stage, N);
+    if (!rc) rc = dev_alloc(c, &c->kf_stage, N * 4);
+    if (!rc) rc = dev_alloc(c, &c->out_stage, N * 2);
+    if (!rc) rc = dev_alloc(c, &c->partial, (size_t)nb * 8);
+    if (!rc) rc = dev_alloc(c, &c->result, 8);
+    if (!rc) rc = dev_alloc(c, &c->health, 1);
+    if (!rc && hipHostMalloc((void**)&c->h_result, 8 * sizeof(double)) != hipSuccess) rc = PIXVOD_ENOMEM;
+    if (!rc && hipHostMalloc((void**)&c->h_health, sizeof(int)) != hipSuccess) rc = PIXVOD_ENOMEM;
+    if (!rc && hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess) rc = PIXVOD_EHIP;
+    if (rc) {
+        std::string m = c->err.empty() ? "context allocation failed" : c->err;
+        release(c);
+        delete c;
+        return fail(nullptr, rc, m);
+    }
+    c->stream = c->own_stream;
+    const Geo g = geo_of(c);
+    const float ell0 = (float)(-std::log((double)P.init_inv_depth));
+    if (launch_init_state(g, c->X[0], ell0, c->stream) != hipSuccess ||
+        launch_init_state(g, c->X[1], ell0, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->var_ll, 0, pl * sizeof(float), c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        release(c);
+        delete c;
+        return fail(nullptr, PIXVOD_EHIP, "state initialisation failed");
+    }
+    *out = c;
+    return PIXVOD_OK;
+}
+
+int pixvod_destroy(pixvod_ctx* c) {
+    if (!c) return PIXVOD_OK;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    release(c);
+    delete c;
+    return PIXVOD_OK;
+}
+
+int pixvod_set_stream(pixvod_ctx* c, void* s) {
+    if (!c) return fail(nullptr, PIXVOD_EINVAL, "ctx is NULL");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->stream = s ? (hipStream_t)s : c->own_stream;
+    return PIXVOD_OK;
+}
+
+int pixvod_set_schedule(pixvod_ctx* c, int schedule) {
+    if (!c) return fail(nullptr, PIXVOD_EINVAL, "ctx is NULL");
+    if (schedule != PIXVOD_SCHED_FUSED && schedule != PIXVOD_SCHED_PER_FACTOR)
+        return fail(c, PIXVOD_EINVAL, "unknown schedule");
+    if (schedule == PIXVOD_SCHED_FUSED && c->P.damping != 0.0f)
+        return fail(c, PIXVOD_EINVAL, "the fused schedule does not support message damping");
+    c->schedule = schedule;
+    return PIXVOD_OK;
+}
+
+static int stage_in(pixvod_ctx* c, const float* src, int where, size_t n, float* stage, const float** out) {
+    if (where == PIXVOD_DEVICE) {
+        *out = src;
+        return PIXVOD_OK;
+    }
+    HIP_TRY(c, hipMemcpyAsync(stage, src, n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    *out = stage;
+    return PIXVOD_OK;
+}
+
+int pixvod_set_keyframe(pixvod_ctx* c, const float* img, const float* normals, int where) {
+    if (!c) return fail(nullptr, PIXVOD_EINVAL, "ctx is NULL");
+    if (!img || !normals) return fail(c, PIXVOD_EINVAL, "img and normals are required");
+    if (where != PIXVOD_HOST && where != PIXVOD_DEVICE) return fail(c, PIXVOD_EINVAL, "bad location");
+    const size_t N = (size_t)c->H * c->W;
+    const float *di = nullptr, *dn = nullptr;
+    int rc = stage_in(c, img, where, N, c->kf_stage, &di);
+    if (rc) return rc;
+    rc = stage_in(c, normals, where, 3 * N, c->kf_stage + N, &dn);
+    if (rc) return rc;
+    const Geo g = geo_of(c);
+    // the canonical state lives in X[cur]; both copies are reset (log-depth kept)
+    float* Xc = c->X[c->cur];
+    float* Xo = c->X[1 - c->cur];
+    HIP_TRY(c, launch_keyframe_prep(g, di, dn, c->Is, c->cxt, c->cyt, Xc, Xo, c->stream));
+    if (c->have_track) {
+        double E[16], Ei[16], Tw[16];
+        host_se3_exp(c->xi_last, E);
+        host_se3_inverse(E, Ei);
+        host_mat4_mul(c->T_w_kf, Ei, Tw);
+        std::memcpy(c->T_w_kf, Tw, sizeof(Tw));
+    }
+    std::memset(c->xi_last, 0, sizeof(c->xi_last));
+    c->have_track = false;
+    c->have_kf = true;
+    c->have_var = false;
+    c->frames_since_kf = 0;
+    if (where == PIXVOD_HOST) HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return PIXVOD_OK;
+}
+
+int pixvod_set_sigma_map(pixvod_ctx* c, const float* map, int where) {
+    if (!c) return fail(nullptr, PIXVOD_EINVAL, "ctx is NULL");
+    if (where != PIXVOD_HOST && where != PIXVOD_DEVICE) return fail(c, PIXVOD_EINVAL, "bad location");
+    if (!map) {
+        c->has_sigma = false;
+        return PIXVOD_OK;
+    }
+    const size_t N = (size_t)c->H * c->W;
+    const float* d = nullptr;
+    int rc = stage_in(c, map, where, N, c->frame_stage, &d);
+    if (rc) return rc;
+    HIP_TRY(c, launch_copy_plane(geo_of(c), d, c->sig, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->has_sigma = true;
+    return PIXVOD_OK;
+}
+
+static int stage_frame(pixvod_ctx* c, const float* frame, int where) {
+    const size_t N = (size_t)c->H * c->W;
+    const float* d = nullptr;
+    int rc = stage_in(c, frame, where, N, c->frame_stage, &d);
+    if (rc) return rc;
+    HIP_TRY(c, launch_frame_prep(geo_of(c), d, c->W, c->It, c->Gx, c->Gy, c->stream));
+    c->have_frame = true;
+    return PIXVOD_OK;
+}
+
+static int run_iterations(pixvod_ctx* c, int n) {
+    if (n <= 0) return PIXVOD_OK;
+    const Geo g = geo_of(c);
+    const Strengths s = strengths_of(c);
+    const Inputs in = inputs_of(c);
+    if (c->schedule == PIXVOD_SCHED_PER_FACTOR) {
+        const size_t pl = (size_t)c->plane;
+        if (!c->marg) {
+            int rc = dev_alloc(c, &c->marg, pl * 29);
+            if (rc) return rc;
+        }
+        if (!c->msg) {
+            int rc = dev_alloc(c, &c->msg, pl * 116);
+            if (rc) return rc;
+        }
+        for (int it = 0; it < n; ++it) {
+            hipEvent_t a = prof_begin(c);
+            HIP_TRY(c, launch_pf_iteration(g, s, in, c->X[c->cur], c->marg, c->msg, c->var_ll, c->valid,
+                                           c->P.damping, c->health, c->stream));
+            prof_end(c, a, PIXVOD_PROF_PER_FACTOR);
+        }
+    } else {
+        int src = c->cur, dst = 1 - c->cur;
+        hipEvent_t a = prof_begin(c);
+        HIP_TRY(c, launch_fu_prologue(g, s, in, c->X[src], c->X[dst], c->health, c->stream));
+        prof_end(c, a, PIXVOD_PROF_FUSED_PROLOGUE);
+        src = dst;
+        for (int it = 0; it < n; ++it) {
+            dst = 1 - src;
+            const bool last = (it == n - 1);
+            a = prof_begin(c);
+            HIP_TRY(c, launch_fu_iterate(g, s, in, c->X[src], c->X[dst], last, c->var_ll, c->valid,
+                                         c->health, c->stream));
+            prof_end(c, a, last ? PIXVOD_PROF_FUSED_FINAL : PIXVOD_PROF_FUSED_ITERATE);
+            src = dst;
+        }
+        c->cur = src;
+    }
+    c->have_var = true;
+    return PIXVOD_OK;
+}
+
+int pixvod_iterate(pixvod_ctx* c, int n) {
+    if (!c) return fail(nullptr, PIXVOD_EINVAL, "ctx is NULL");
+    if (n < 0) return fail(c, PIXVOD_EINVAL, "n_iters must be >= 0");
+    if (!c->have_kf || !c->have_frame) return fail(c, PIXVOD_ESTATE, "no keyframe or frame staged");
+    return run_iterations(c, n);
+}
+
+int pixvod_track(pixvod_ctx* c, const float* frame, int where, int n_iters, pixvod_track_out* out) {
+    if (!c) return fail(nullptr, PIXVOD_EINVAL, "ctx is NULL");
+    if (!frame || !out) return fail(c, PIXVOD_EINVAL, "frame and out are required");
+    if (where != PIXVOD_HOST && where != PIXVOD_DEVICE) return fail(c, PIXVOD_EINVAL, "bad location");
+    if (out->out_where != PIXVOD_HOST && out->out_where != PIXVOD_DEVICE)
+        return fail(c, PIXVOD_EINVAL, "bad output location");
+    if (n_iters < 0) return fail(c, PIXVOD_EINVAL, "n_iters must be >= 0");
+    if (!c->have_kf) return fail(c, PIXVOD_ESTATE, "pixvod_track before pixvod_set_keyframe");
+    const Geo g = geo_of(c);
+    const size_t N = (size_t)c->H * c->W;
+    int rc = stage_frame(c, frame, where);
+    if (rc) return rc;
+    HIP_TRY(c, hipMemsetAsync(c->health, 0, sizeof(int), c->stream));
+    if (n_iters == 0) {
+        HIP_TRY(c, launch_valid_only(g, strengths_of(c), inputs_of(c), c->X[c->cur], c->valid, c->stream));
+        c->have_var = false;
+    } else {
+        rc = run_iterations(c, n_iters);
+        if (rc) return rc;
+    }
+    HIP_TRY(c, launch_frame_stats(g, c->X[c->cur], c->valid, 1, c->partial, c->result, c->stream));
+    if (out->inv_depth || out->inv_depth_var) {
+        float* d_inv = out->inv_depth;
+        float* d_var = out->inv_depth_var;
+        if (out->out_where == PIXVOD_HOST) {
+            d_inv = out->inv_depth ? c->out_stage : nullptr;
+            d_var = out->inv_depth_var ? c->out_stage + N : nullptr;
+        }
+        HIP_TRY(c, launch_outputs(g, c->X[c->cur], c->var_ll, c->have_var ? 1 : 0, d_inv, d_var, c->stream));
+        if (out->out_where == PIXVOD_HOST) {
+            if (out->inv_depth)
+                HIP_TRY(c, hipMemcpyAsync(out->inv_depth, c->out_stage, N * sizeof(float), hipMemcpyDeviceToHost,
+                                          c->stream));
+            if (out->inv_depth_var)
+                HIP_TRY(c, hipMemcpyAsync(out->inv_depth_var, c->out_stage + N, N * sizeof(float),
+                                          hipMemcpyDeviceToHost, c->stream));
+        }
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->h_result, c->result, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->h_health, c->health, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (!c->pending.empty()) prof_collect(c);
+
+    const double inv_n = 1.0 / (double)N;
+    for (int k = 0; k < 6; ++k) {
+        c->xi_last[k] = c->h_result[k] * inv_n;
+        out->xi_rel[k] = c->xi_last[k];
+    }
+    c->have_track = true;
+    c->frames_since_kf += 1;
+    double E[16], Ei[16];
+    host_se3_exp(c->xi_last, E);
+    host_se3_inverse(E, Ei);
+    host_mat4_mul(c->T_w_kf, Ei, out->T_world);
+    const float vf = (float)(c->h_result[6] * inv_n);
+    out->valid_fraction = vf;
+    out->frames_since_keyframe = c->frames_since_kf;
+    unsigned f = 0;
+    if (c->frames_since_kf >= c->P.kf_max_frames || vf < c->P.kf_min_valid_frac) f |= PIXVOD_KEYFRAME_DUE;
+    if (vf < c->P.kf_min_valid_frac) f |= PIXVOD_LOW_OVERLAP;
+    if (c->h_result[7] > 0.0 || *c->h_health != 0) f |= PIXVOD_DIVERGED;
+    out->flags = f;
+    return PIXVOD_OK;
+}
+
+int pixvod_profile_enable(pixvod_ctx* c, int enable) {
+    if (!c) return fail(nullptr, PIXVOD_EINVAL, "ctx is NULL");
+    c->prof = enable != 0;
+    return PIXVOD_OK;
+}
+
+int pixvod_profile_read(pixvod_ctx* c, int kind, double* total_ms, int64_t* launches) {
+    if (!c) return fail(nullptr, PIXVOD_EINVAL, "ctx is NULL");
+    if (kind < 0 || kind >= PIXVOD_PROF_KINDS || !total_ms || !launches)
+        return fail(c, PIXVOD_EINVAL, "bad profile query");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    prof_collect(c);
+    *total_ms = c->prof_ms[kind];
+    *launches = c->prof_n[kind];
+    c->prof_ms[kind] = 0.0;
+    c->prof_n[kind] = 0;
+    return PIXVOD_OK;
+}
+
+int pixvod_state_bytes(const pixvod_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return fail(const_cast<pixvod_ctx*>(c), PIXVOD_EINVAL, "ctx and bytes are required");
+    *bytes = (size_t)N_PLANES * c->H * c->W * sizeof(float);
+    return PIXVOD_OK;
+}
+
+static int ensure_dense(pixvod_ctx* c) {
+    if (c->dense_state) return PIXVOD_OK;
+    return dev_alloc(c, &c->dense_state, (size_t)N_PLANES * c->H * c->W);
+}
+
+int pixvod_get_state(pixvod_ctx* c, void* dst, int where) {
+    if (!c) return fail(nullptr, PIXVOD_EINVAL, "ctx is NULL");
+    if (!dst) return fail(c, PIXVOD_EINVAL, "dst is NULL");
+    if (where != PIXVOD_HOST && where != PIXVOD_DEVICE) return fail(c, PIXVOD_EINVAL, "bad location");
+    const size_t n = (size_t)N_PLANES * c->H * c->W;
+    float* d = (float*)dst;
+    if (where == PIXVOD_HOST) {
+        int rc = ensure_dense(c);
+        if (rc) return rc;
+        d = c->dense_state;
+    }
+    HIP_TRY(c, launch_pack_state(geo_of(c), c->X[c->cur], d, 1, c->stream));
+    if (where == PIXVOD_HOST)
+        HIP_TRY(c, hipMemcpyAsync(dst, d, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return PIXVOD_OK;
+}
+
+int pixvod_set_state(pixvod_ctx* c, const void* src, int where) {
+    if (!c) return fail(nullptr, PIXVOD_EINVAL, "ctx is NULL");
+    if (!src) return fail(c, PIXVOD_EINVAL, "src is NULL");
+    if (where != PIXVOD_HOST && where != PIXVOD_DEVICE) return fail(c, PIXVOD_EINVAL, "bad location");
+    const size_t n = (size_t)N_PLANES * c->H * c->W;
+    const float* d = (const float*)src;
+    if (where == PIXVOD_HOST) {
+        int rc = ensure_dense(c);
+        if (rc) return rc;
+        HIP_TRY(c, hipMemcpyAsync(c->dense_state, src, n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+        d = c->dense_state;
+    }
+    HIP_TRY(c, launch_pack_state(geo_of(c), c->X[c->cur], const_cast<float*>(d), 0, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return PIXVOD_OK;
+}
+
+}  // extern "C"

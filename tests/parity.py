@@ -1,0 +1,97 @@
+"""Shared helpers of the parity tests: workloads, state layout conversion and
+the agreement measures.
+
+Parity bar:
+  pose (mean per-pixel se(3) vector)   |xi_gpu - xi_oracle|_inf <= 1e-5
+  inverse depth                         relative RMS and 99th percentile of
+                                        |rho_gpu - rho_or| / rho_or <= 1e-4
+The state is FP32 on the GPU and FP64 in the oracle. The iteration amplifies
+small differences (the FP64 oracle itself turns a 1e-12 perturbation of the
+log-depths into ~1e-6 pose differences within two frames on the textured
+sequences), so:
+  * every iteration is checked teacher-forced: oracle and GPU start from the
+    same FP32 state and all 123 planes are compared after one iteration;
+  * free-running runs are compared over horizons where the iteration is not
+    chaotic (one frame of the sequences, the tiny pair at sigma_P = 0.1);
+  * the per-pixel maximum is reported and bounded loosely (a handful of
+    ill-conditioned pixels).
+"""
+
+from __future__ import annotations
+
+import math
+from typing import Dict, List
+
+import numpy as np
+
+import oracle
+import synth
+from synth.scenes import SEQUENCE_CONFIGS, make_sequence_scene, render_sequence_frame, sequence_poses
+
+POSE_TOL = 1e-5
+DEPTH_TOL = 1e-4
+
+# factor strengths per workload: the paper's leaf values except the prior,
+# which on the flat grid is the weakest decade value whose early iterations
+# stay stable (the paper's selection rule for the prior)
+SEQ_PARAMS = {
+    "ppa256": dict(sigma_P=0.01, huber_k=400.0),
+    "vga": dict(sigma_P=0.01, huber_k=10.0),
+    "diff320": dict(sigma_P=0.01, huber_k=10.0),
+}
+
+
+def to_oracle(state: np.ndarray) -> np.ndarray:
+    """(123, H, W) float32 exchange layout -> (H, W, 123) float64."""
+    return np.ascontiguousarray(np.transpose(state.astype(np.float64), (1, 2, 0)))
+
+
+def from_oracle(state: np.ndarray) -> np.ndarray:
+    return np.ascontiguousarray(np.transpose(state, (2, 0, 1)).astype(np.float32))
+
+
+def depth_agreement(rho_gpu: np.ndarray, rho_or: np.ndarray) -> Dict[str, float]:
+    e = np.abs(rho_gpu.astype(np.float64) - rho_or) / np.abs(rho_or)
+    return dict(rms=float(np.sqrt(np.mean(e * e))), p99=float(np.percentile(e, 99)),
+                max=float(e.max()), frac_over=float(np.mean(e > DEPTH_TOL)))
+
+
+def pose_agreement(xi_gpu, xi_or) -> float:
+    return float(np.abs(np.asarray(xi_gpu) - np.asarray(xi_or)).max())
+
+
+def tiny_workload(seed=0, huber_k=400.0, sigma_P=0.1):
+    p = synth.tiny_pair(seed)
+    cam = p["cam"]
+    kw = dict(init_inv_depth=0.3, huber_k=huber_k, sigma_P=sigma_P)
+    return dict(cam=cam, I_s=p["I_s"], N_s=p["normals_s"], frames=[p["I_t"]], iters=50, kw=kw)
+
+
+def sequence_workload(name: str, n_frames: int, first: int = 1):
+    cfg = SEQUENCE_CONFIGS[name]
+    scene, cam = make_sequence_scene(cfg)
+    poses = sequence_poses(cfg)
+    I0, D0, N0, _ = render_sequence_frame(cfg, scene, cam, poses, 0, keyframe=True)
+    frames = [render_sequence_frame(cfg, scene, cam, poses, f)[0] for f in range(first, first + n_frames)]
+    iters = {"ppa256": 20, "vga": 20, "diff320": 30}[name]
+    return dict(cam=cam, I_s=I0, N_s=N0, frames=frames, iters=iters, kw=dict(SEQ_PARAMS[name]),
+                depth0=D0, poses=poses)
+
+
+def K_of(cam):
+    return (cam.fx, cam.fy, cam.cx, cam.cy)
+
+
+def make_oracle(w) -> "oracle.Oracle":
+    o = oracle.Oracle(oracle.config_for_camera(w["cam"], **w["kw"]))
+    o.set_keyframe(w["I_s"], w["N_s"])
+    return o
+
+
+def make_tracker(w, schedule=0):
+    import paper_2606_03989_amd as pv
+    cam = w["cam"]
+    t = pv.Tracker(cam.H, cam.W, K_of(cam), **w["kw"])
+    t.set_schedule(schedule)
+    t.set_keyframe(w["I_s"], w["N_s"])
+    return t

@@ -1,0 +1,274 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle on the
+same seeded inputs."""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from parity import (DEPTH_TOL, POSE_TOL, depth_agreement, from_oracle, make_oracle, make_tracker,
+                    pose_agreement, sequence_workload, tiny_workload, to_oracle)
+
+pytestmark = pytest.mark.gpu
+
+SCHEDULES = [0, 1]   # fused, per-factor
+
+
+def _run_both(w, schedule, n_frames=None):
+    t = make_tracker(w, schedule)
+    o = make_oracle(w)
+    out = []
+    frames = w["frames"] if n_frames is None else w["frames"][:n_frames]
+    for f in frames:
+        rg = t.track(f, w["iters"])
+        ro = o.track(f, w["iters"])
+        out.append((rg, ro))
+    return t, o, out
+
+
+def _assert_frame(rg, ro, name, depth_max=5e-2):
+    dp = pose_agreement(rg["xi"], ro["xi"])
+    da = depth_agreement(rg["inv_depth"], ro["inv_depth"])
+    print(f"{name}: pose {dp:.2e} depth rms {da['rms']:.2e} p99 {da['p99']:.2e} max {da['max']:.2e} "
+          f"frac>tol {da['frac_over']:.2e} valid {rg['valid_fraction']:.4f}/{ro['valid_fraction']:.4f}", flush=True)
+    assert dp <= POSE_TOL
+    assert da["rms"] <= DEPTH_TOL and da["p99"] <= DEPTH_TOL
+    assert da["max"] <= depth_max
+    assert abs(rg["valid_fraction"] - ro["valid_fraction"]) <= 2e-3
+    assert (rg["flags"] & oracle.DIVERGED) == (ro["flags"] & oracle.DIVERGED)
+
+
+# --- one iteration from an identical state ---------------------------------------
+
+def _one_step(t, o, state32, frame):
+    """Loads the same FP32 state into both, one iteration, returns (gpu, oracle)
+    states in the exchange layout (oracle rounded to FP32)."""
+    t.set_state(state32)
+    o.set_state(to_oracle(state32))
+    o.set_frame(frame)
+    t.iterate(1)
+    o.iterate(1)
+    return t.get_state(), from_oracle(o.get_state())
+
+
+def _plane_errors(g, r):
+    g = g.astype(np.float64)
+    r = r.astype(np.float64)
+    scale = np.abs(r).reshape(123, -1).max(axis=1)[:, None, None] + 1e-30
+    return np.abs(g - r) / scale
+
+
+SINGLE_CASES = {
+    # name: (workload factory, p99.9 bound, fraction of elements above 1e-5)
+    "tiny_sigmaP1": (lambda: tiny_workload(sigma_P=1.0), 1e-3, 2e-2),
+    "tiny": (lambda: tiny_workload(huber_k=10.0), 1e-5, 1e-3),
+    "ppa256": (lambda: sequence_workload("ppa256", 1), 1e-5, 2e-3),
+}
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
+@pytest.mark.parametrize("case", list(SINGLE_CASES))
+def test_single_iteration_from_identical_state(case, schedule):
+    make, p999, frac_bound = SINGLE_CASES[case]
+    w = make()
+    # a non-trivial state: the oracle after a few iterations, rounded to FP32
+    o = make_oracle(w)
+    o.track(w["frames"][0], 3)
+    s32 = from_oracle(o.get_state())
+    t = make_tracker(w, schedule)
+    t.track(w["frames"][0], 0)          # stages the frame
+    t.set_state(s32)
+    np.testing.assert_array_equal(t.get_state(), s32)
+    g, r = _one_step(t, o, s32, w["frames"][0])
+    err = _plane_errors(g, r)
+    worst = np.unravel_index(np.argmax(err), err.shape)
+    q = float(np.percentile(err, 99.9))
+    frac = float(np.mean(err > 1e-5))
+    print(f"{case}/{schedule}: plane-relative error p99.9 {q:.2e} max {err.max():.2e} at {worst} "
+          f"frac>1e-5 {frac:.2e}", flush=True)
+    assert q <= p999 and frac <= frac_bound
+
+
+def test_teacher_forced_iterations_ppa256():
+    # every iteration of the first frame starts the oracle from the GPU's state
+    w = sequence_workload("ppa256", 1)
+    t = make_tracker(w, 0)
+    o = make_oracle(w)
+    t.track(w["frames"][0], 0)
+    o.set_frame(w["frames"][0])
+    worst = 0.0
+    for it in range(w["iters"]):
+        s32 = t.get_state()
+        o.set_state(to_oracle(s32))
+        t.iterate(1)
+        o.iterate(1)
+        err = _plane_errors(t.get_state(), from_oracle(o.get_state()))
+        q = float(np.percentile(err, 99.9))
+        worst = max(worst, q)
+        assert q <= 1e-5, f"iteration {it}: p99.9 {q:.2e}"
+    print(f"ppa256 teacher-forced 20 iterations: worst p99.9 {worst:.2e}", flush=True)
+
+
+# --- free-running parity ---------------------------------------------------------
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
+@pytest.mark.parametrize("huber_k", [400.0, 10.0])
+def test_tiny_pair_50_iterations(schedule, huber_k):
+    w = tiny_workload(huber_k=huber_k)
+    t, o, out = _run_both(w, schedule)
+    rg, ro = out[0]
+    _assert_frame(rg, ro, f"tiny k={huber_k} sched={schedule}")
+    # outputs: variance of the final belief, finite and positive
+    assert np.all(np.isfinite(rg["inv_depth_var"])) and np.all(rg["inv_depth_var"] > 0)
+    np.testing.assert_allclose(rg["inv_depth_var"], ro["inv_depth_var"], rtol=1e-3)
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_ppa256_frame_1(schedule):
+    w = sequence_workload("ppa256", 1)
+    t, o, out = _run_both(w, schedule)
+    _assert_frame(out[0][0], out[0][1], f"ppa256 frame 1 sched={schedule}")
+
+
+def test_ppa256_teacher_forced_frames():
+    # frames 2-3 start the oracle from the GPU's state at the frame boundary
+    w = sequence_workload("ppa256", 3)
+    t = make_tracker(w, 0)
+    o = make_oracle(w)
+    t.track(w["frames"][0], w["iters"])
+    o.track(w["frames"][0], 0)
+    for k in (1, 2):
+        o.set_state(to_oracle(t.get_state()))
+        rg = t.track(w["frames"][k], w["iters"])
+        ro = o.track(w["frames"][k], w["iters"])
+        assert rg["frames_since_keyframe"] == ro["frames_since_keyframe"] == k + 1
+        _assert_frame(rg, ro, f"ppa256 frame {k + 1} teacher-forced")
+
+
+def test_vga_frame_1():
+    w = sequence_workload("vga", 1)
+    t, o, out = _run_both(w, 0)
+    _assert_frame(out[0][0], out[0][1], "vga frame 1")
+
+
+@pytest.mark.parametrize("case", ["tiny", "ppa256"])
+def test_schedules_agree(case):
+    # the fused and per-factor schedules evaluate the same arithmetic
+    w = tiny_workload(huber_k=10.0) if case == "tiny" else sequence_workload("ppa256", 1)
+    res = []
+    for sched in SCHEDULES:
+        t = make_tracker(w, sched)
+        r = t.track(w["frames"][0], 10)
+        res.append((r, t.get_state()))
+    same = np.array_equal(res[0][1], res[1][1])
+    d = np.abs(res[0][1].astype(np.float64) - res[1][1]).reshape(123, -1).max(axis=1)
+    scale = np.abs(res[1][1]).reshape(123, -1).max(axis=1) + 1e-30
+    print(f"{case}: schedules bit-identical: {same}; max plane-relative difference {(d / scale).max():.2e}", flush=True)
+    assert pose_agreement(res[0][0]["xi"], res[1][0]["xi"]) <= 1e-7
+    assert np.all(d / scale < 1e-4)
+
+
+def test_damping_per_factor_schedule():
+    w = tiny_workload(sigma_P=0.1)
+    w["kw"]["damping"] = 0.3
+    t = make_tracker(w, 1)
+    o = make_oracle(w)
+    rg = t.track(w["frames"][0], 30)
+    ro = o.track(w["frames"][0], 30)
+    _assert_frame(rg, ro, "tiny damping 0.3")
+
+
+# --- the boundary's behaviour on the GPU --------------------------------------------------
+
+def test_errors_and_states():
+    import paper_2606_03989_amd as pv
+    w = tiny_workload()
+    cam = w["cam"]
+    t = pv.Tracker(cam.H, cam.W, (cam.fx, cam.fy, cam.cx, cam.cy))
+    with pytest.raises(pv.PixvodError) as e:
+        t.track(w["frames"][0], 5)
+    assert e.value.code == pv.ESTATE
+    with pytest.raises(pv.PixvodError) as e:
+        t.set_schedule(7)
+    assert e.value.code == pv.EINVAL
+    td = pv.Tracker(cam.H, cam.W, (cam.fx, cam.fy, cam.cx, cam.cy), damping=0.5)
+    with pytest.raises(pv.PixvodError) as e:
+        td.set_schedule(pv.SCHED_FUSED)
+    assert e.value.code == pv.EINVAL
+    assert t.state_bytes() == 123 * cam.H * cam.W * 4
+
+
+def test_zero_iterations_and_reanchoring():
+    w = tiny_workload()
+    w["kw"]["kf_max_frames"] = 2
+    t = make_tracker(w, 0)
+    o = make_oracle(w)
+    r0 = t.track(w["frames"][0], 0)
+    assert r0["valid_fraction"] == 1.0 and np.all(np.isnan(r0["inv_depth_var"]))
+    np.testing.assert_allclose(r0["inv_depth"], 0.3, rtol=1e-6)
+    o.track(w["frames"][0], 0)
+    rg = t.track(w["frames"][0], 20)
+    ro = o.track(w["frames"][0], 20)
+    assert rg["flags"] & oracle.KEYFRAME_DUE and ro["flags"] & oracle.KEYFRAME_DUE
+    t.set_keyframe(w["frames"][0], w["N_s"])
+    o.set_keyframe(w["frames"][0], w["N_s"])
+    rg = t.track(w["frames"][0], 5)
+    ro = o.track(w["frames"][0], 5)
+    assert rg["frames_since_keyframe"] == 1
+    np.testing.assert_allclose(rg["T_world"], ro["T_world"], atol=1e-5)
+
+
+def test_device_pointers_match_host_pointers():
+    import torch
+    w = tiny_workload(huber_k=10.0)
+    t1 = make_tracker(w, 0)
+    r1 = t1.track(w["frames"][0], 10)
+    import paper_2606_03989_amd as pv
+    cam = w["cam"]
+    t2 = pv.Tracker(cam.H, cam.W, (cam.fx, cam.fy, cam.cx, cam.cy), **w["kw"])
+    t2.set_stream(torch.cuda.current_stream())
+    t2.set_keyframe(torch.from_numpy(w["I_s"]).cuda(), torch.from_numpy(np.ascontiguousarray(w["N_s"])).cuda())
+    r2 = t2.track(torch.from_numpy(w["frames"][0]).cuda(), 10, out_device=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(r1["xi"], r2["xi"])
+    np.testing.assert_array_equal(r1["inv_depth"], r2["inv_depth"].cpu().numpy())
+
+
+@pytest.mark.parametrize("shape", [(2, 2), (3, 70), (29, 37), (65, 5)])
+def test_ragged_and_minimal_shapes(shape):
+    import synth
+    H, W = shape
+    p = synth.tiny_pair(7, H=H, W=W)
+    w = dict(cam=p["cam"], I_s=p["I_s"], N_s=p["normals_s"], frames=[p["I_t"]], iters=8,
+             kw=dict(init_inv_depth=0.4, huber_k=10.0, sigma_P=0.1))
+    for sched in SCHEDULES:
+        t = make_tracker(w, sched)
+        o = make_oracle(w)
+        rg = t.track(w["frames"][0], 8)
+        ro = o.track(w["frames"][0], 8)
+        _assert_frame(rg, ro, f"shape {shape} sched={sched}")
+
+
+def test_constant_image_keeps_pose_at_identity():
+    import synth
+    p = synth.tiny_pair(0)
+    flat = np.full(p["I_s"].shape, 0.4, np.float32)
+    w = dict(cam=p["cam"], I_s=flat, N_s=p["normals_s"], frames=[flat], iters=10, kw=dict(init_inv_depth=0.3))
+    t = make_tracker(w, 0)
+    r = t.track(flat, 10)
+    s = t.get_state()
+    assert np.all(s[:6] == 0) and np.all(r["xi"] == 0)
+
+
+def test_sigma_map_matches_oracle():
+    w = tiny_workload(huber_k=10.0)
+    rng = np.random.default_rng(3)
+    sig = (5e-3 * np.exp(rng.normal(0, 0.3, size=w["I_s"].shape))).astype(np.float32)
+    t = make_tracker(w, 0)
+    t.set_sigma_map(sig)
+    o = make_oracle(w)
+    o.set_sigma_D_map(sig.astype(np.float64))
+    rg = t.track(w["frames"][0], 30)
+    ro = o.track(w["frames"][0], 30)
+    _assert_frame(rg, ro, "sigma map")

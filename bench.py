@@ -179,6 +179,32 @@ def cpu_baseline(iters: int):
                 sample=f"frame 1 of the 640x480 sequence, {iters} GBP iterations ({b - a:.1f} s)")
 
 
+def probe(frames: int = 3, copy_mb: int = 512):
+    """Short run for hardware-counter collection: the fused schedule on a few
+    frames, one per-factor frame, and a plain device copy of known size that
+    calibrates the byte counters."""
+    import torch
+    import paper_2606_03989_amd as pv
+    cam, I0, N0, fr, _ = vga_inputs(frames)
+    dev = torch.device("cuda:0")
+    d_fr = [torch.from_numpy(f).to(dev) for f in fr]
+    for sched in (pv.SCHED_FUSED, pv.SCHED_PER_FACTOR):
+        t = pv.Tracker(cam.H, cam.W, (cam.fx, cam.fy, cam.cx, cam.cy), **VGA_PARAMS)
+        t.set_stream(torch.cuda.current_stream())
+        t.set_schedule(sched)
+        t.set_keyframe(torch.from_numpy(I0).to(dev), torch.from_numpy(N0).to(dev))
+        for f in (d_fr if sched == pv.SCHED_FUSED else d_fr[:1]):
+            t.track(f, 20, maps=False)
+        t.close()
+    n = copy_mb * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"probe done: copy calibration {copy_mb} MiB read + {copy_mb} MiB written per copy, 3 copies")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,7 +214,11 @@ def main():
     ap.add_argument("--per-factor-steps", type=int, default=3)
     ap.add_argument("--cpu-iters", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--probe", action="store_true", help="short run for hardware counters; no JSON line")
     args = ap.parse_args()
+    if args.probe:
+        probe()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (single-GPU build)", file=sys.stderr)
         sys.exit(2)

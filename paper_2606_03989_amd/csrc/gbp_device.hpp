@@ -46,6 +46,7 @@ struct Strengths {
     double lamR;          // identity
     double lamN;          // normal integration
     double lamD;          // photometric, used when no sigma map is bound
+    double inv_sigD;      // 1 / sigma_D, likewise
     double huber_k;
     double prior_ell;
     double prior_R[9];    // Exp(prior_xi)^-1 rotation
@@ -72,6 +73,25 @@ __device__ inline void skew_mul(const double w[3], const double v[3], double out
     out[0] = w[1] * v[2] - w[2] * v[1];
     out[1] = w[2] * v[0] - w[0] * v[2];
     out[2] = w[0] * v[1] - w[1] * v[0];
+}
+
+// 1/x and 1/sqrt(x) in double precision: the hardware estimate refined by two
+// Newton steps (quadratic convergence from the ~2^-22 estimate to rounding)
+__device__ inline double rcp_nr(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
+__device__ inline double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    double e = fma(-h * y, y, 0.5);
+    y = fma(y, e, y);
+    e = fma(-h * y, y, 0.5);
+    return fma(y, e, y);
 }
 
 // R = I + A W + B W^2 and V = I + B W + C W^2 with W = [theta]x
@@ -109,46 +129,66 @@ __device__ inline void se3_exp(const double xi[6], double R[9], double t[3]) {
     for (int r = 0; r < 3; ++r) t[r] = V[r * 3] * xi[3] + V[r * 3 + 1] * xi[4] + V[r * 3 + 2] * xi[5];
 }
 
-__device__ inline void so3_log(const double R[9], double w[3]) {
+// theta / sin(theta) as a series in s^2 = sin^2(theta), valid for cos > 0:
+// asin(s)/s = sum_k (2k)! / (4^k (k!)^2 (2k+1)) s^(2k); truncation < 2e-18
+// for s <= 0.1
+__device__ inline double asin_over_s(double s2) {
+    double p = 143.0 / 10240.0;
+    p = fma(p, s2, 231.0 / 13312.0);
+    p = fma(p, s2, 63.0 / 2816.0);
+    p = fma(p, s2, 35.0 / 1152.0);
+    p = fma(p, s2, 5.0 / 112.0);
+    p = fma(p, s2, 3.0 / 40.0);
+    p = fma(p, s2, 1.0 / 6.0);
+    return fma(p, s2, 1.0);
+}
+
+// w = Log(R); th2 receives theta^2
+__device__ inline void so3_log(const double R[9], double w[3], double& th2) {
     const double v0 = R[7] - R[5], v1 = R[2] - R[6], v2 = R[3] - R[1];
-    const double s = 0.5 * sqrt(v0 * v0 + v1 * v1 + v2 * v2);
-    const double c = 0.5 * (R[0] + R[4] + R[8] - 1.0);
-    const double th = atan2(s, c);
-    double f;
-    if (th < 1e-4) {
-        const double t2 = th * th;
-        f = 0.5 * (1.0 + t2 * (1.0 / 6.0) + t2 * t2 * (7.0 / 360.0));
-    } else if (th < 3.14149265358979) {
-        f = th / (2.0 * sin(th));
-    } else {
-        // near pi: axis from the diagonal (not reached by tracking motions)
-        double n[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const double d = (R[i * 4] + 1.0) * 0.5;
-            n[i] = sqrt(d > 0.0 ? d : 0.0);
-        }
-        const int k = (n[0] >= n[1] && n[0] >= n[2]) ? 0 : (n[1] >= n[2] ? 1 : 2);
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-            if (i != k) n[i] = (R[i * 3 + k] + R[k * 3 + i]) / (4.0 * n[k]);
-        double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-        if (n[0] * v0 + n[1] * v1 + n[2] * v2 < 0.0) nn = -nn;
-        w[0] = th * n[0] / nn;
-        w[1] = th * n[1] / nn;
-        w[2] = th * n[2] / nn;
+    const double s2 = 0.25 * (v0 * v0 + v1 * v1 + v2 * v2);     // sin^2(theta)
+    const double c = 0.5 * (R[0] + R[4] + R[8] - 1.0);          // cos(theta)
+    if (s2 < 1e-2 && c > 0.0) {
+        const double g = asin_over_s(s2);                       // theta / sin(theta)
+        th2 = s2 * g * g;
+        const double f = 0.5 * g;
+        w[0] = f * v0;
+        w[1] = f * v1;
+        w[2] = f * v2;
         return;
     }
-    w[0] = f * v0;
-    w[1] = f * v1;
-    w[2] = f * v2;
+    const double s = sqrt(s2);
+    const double th = atan2(s, c);
+    th2 = th * th;
+    if (th < 3.14149265358979) {
+        const double f = th / (2.0 * s);
+        w[0] = f * v0;
+        w[1] = f * v1;
+        w[2] = f * v2;
+        return;
+    }
+    // near pi: axis from the diagonal (not reached by tracking motions)
+    double n[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double d = (R[i * 4] + 1.0) * 0.5;
+        n[i] = sqrt(d > 0.0 ? d : 0.0);
+    }
+    const int k = (n[0] >= n[1] && n[0] >= n[2]) ? 0 : (n[1] >= n[2] ? 1 : 2);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        if (i != k) n[i] = (R[i * 3 + k] + R[k * 3 + i]) / (4.0 * n[k]);
+    double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    if (n[0] * v0 + n[1] * v1 + n[2] * v2 < 0.0) nn = -nn;
+    w[0] = th * n[0] / nn;
+    w[1] = th * n[1] / nn;
+    w[2] = th * n[2] / nn;
 }
 
 // xi = Log([R | t]); translation part rho = V^-1 t, V^-1 = I - W/2 + D W^2
 __device__ inline void se3_log(const double R[9], const double t[3], double xi[6]) {
-    so3_log(R, xi);
-    const double w0 = xi[0], w1 = xi[1], w2 = xi[2];
-    const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
+    double th2;
+    so3_log(R, xi, th2);
     double D;
     if (th2 < 1e-2) {
         const double t4 = th2 * th2, t6 = t4 * th2, t8 = t4 * t4;
@@ -205,9 +245,9 @@ __device__ inline bool chol6(double A[21], double inv_diag[6]) {
 #pragma unroll
         for (int k = 0; k < j; ++k) d -= A[s6(j, k)] * A[s6(j, k)];
         ok = ok && (d > 0.0);
-        const double l = sqrt(d > 0.0 ? d : 1e-300);
-        const double il = 1.0 / l;
-        A[s6(j, j)] = l;
+        const double dd = d > 0.0 ? d : 1e-300;
+        const double il = rsqrt_nr(dd);
+        A[s6(j, j)] = dd * il;
         inv_diag[j] = il;
 #pragma unroll
         for (int i = j + 1; i < 6; ++i) {
@@ -271,9 +311,9 @@ __device__ inline bool chol7(double A[28], double inv_diag[7]) {
 #pragma unroll
         for (int k = 0; k < j; ++k) d -= A[s7(j, k)] * A[s7(j, k)];
         ok = ok && (d > 0.0);
-        const double l = sqrt(d > 0.0 ? d : 1e-300);
-        const double il = 1.0 / l;
-        A[s7(j, j)] = l;
+        const double dd = d > 0.0 ? d : 1e-300;
+        const double il = rsqrt_nr(dd);
+        A[s7(j, j)] = dd * il;
         inv_diag[j] = il;
 #pragma unroll
         for (int i = j + 1; i < 7; ++i) {
@@ -352,7 +392,7 @@ __device__ inline bool unary_factors(const Geo& g, const Strengths& s, const Inp
     const double a2 = R[6] * q0 + R[7] * q1 + R[8] + rho * t[2];
     bool valid = false;
     if (a2 > 0.0) {
-        const double iz = 1.0 / a2;
+        const double iz = rcp_nr(a2);
         const double wx = g.fx * a0 * iz + g.cx, wy = g.fy * a1 * iz + g.cy;
         if (wx >= -WARP_EPS && wx <= (g.W - 1) + WARP_EPS && wy >= -WARP_EPS && wy <= (g.H - 1) + WARP_EPS) {
             valid = true;
@@ -379,9 +419,14 @@ __device__ inline bool unary_factors(const Geo& g, const Strengths& s, const Inp
             J[4] = rho * b1;
             J[5] = rho * b2;
             J[6] = -rho * (c0 * t[0] + c1 * t[1] + c2 * t[2]);
-            const double lamD = s.has_sigma_map ? 1.0 / ((double)in.sigD[pix] * (double)in.sigD[pix]) : s.lamD;
-            const double M = fabs(r) * sqrt(lamD);
-            const double kappa = (M <= s.huber_k) ? 1.0 : (2.0 * s.huber_k / M - (s.huber_k * s.huber_k) / (M * M));
+            const double isig = s.has_sigma_map ? rcp_nr((double)in.sigD[pix]) : s.inv_sigD;
+            const double lamD = isig * isig;
+            const double M = fabs(r) * isig;
+            double kappa = 1.0;
+            if (M > s.huber_k) {
+                const double iM = rcp_nr(M);
+                kappa = s.huber_k * iM * (2.0 - s.huber_k * iM);
+            }
             const double w = kappa * lamD;
 #pragma unroll
             for (int a = 0; a < 7; ++a) {
@@ -432,16 +477,21 @@ __device__ inline bool unary_factors(const Geo& g, const Strengths& s, const Inp
                 Jp[(r + 3) * 6 + c + 3] = top;
             }
     }
+    // J^T J and J^T r with J = [[S, 0], [Q, S]] (S top-left block, Q bottom-left)
     const double lamP = s.lamP;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const double rk = lamP * rp[k];
+    for (int a = 0; a < 6; ++a) {
+        double e = 0.0;
 #pragma unroll
-        for (int a = 0; a < 6; ++a) {
-            const double lJa = lamP * Jp[k * 6 + a];
-            eta[a] -= Jp[k * 6 + a] * rk;
+        for (int k = (a < 3 ? 0 : 3); k < 6; ++k) e += Jp[k * 6 + a] * rp[k];
+        eta[a] -= lamP * e;
 #pragma unroll
-            for (int b = a; b < 6; ++b) L[s7(a, b)] += lJa * Jp[k * 6 + b];
+        for (int b = a; b < 6; ++b) {
+            double g = 0.0;
+            const int k0 = (a < 3 && b < 3) ? 0 : 3;
+#pragma unroll
+            for (int k = k0; k < 6; ++k) g += Jp[k * 6 + a] * Jp[k * 6 + b];
+            L[s7(a, b)] += lamP * g;
         }
     }
     eta[6] -= lamP * (ell - s.prior_ell);
@@ -454,7 +504,7 @@ __device__ inline bool unary_factors(const Geo& g, const Strengths& s, const Inp
 
 // pose marginal (depth eliminated): P = L_pp - L_p6 L_6p / L_66
 __device__ inline void pose_marginal(const double L[28], const double eta[7], double P[21], double p[6]) {
-    const double i66 = 1.0 / L[s7(6, 6)];
+    const double i66 = rcp_nr(L[s7(6, 6)]);
 #pragma unroll
     for (int r = 0; r < 6; ++r) {
         const double lr = L[s7(r, 6)] * i66;
@@ -522,7 +572,7 @@ __device__ inline bool identity_partial(double lamR, double V[21], const double 
 //   lambda' = lamN ls / (lamN + ls),  h = lamN vs / (lamN + ls),
 //   eta' = h - lambda' r_recv with r_recv the residual as seen by the receiver.
 __device__ inline void normal_partial(double lamN, double ls, double vs, double& lp, double& h) {
-    const double inv = 1.0 / (lamN + ls);
+    const double inv = rcp_nr(lamN + ls);
     lp = lamN * ls * inv;
     h = lamN * vs * inv;
 }

@@ -145,6 +145,7 @@ static Strengths strengths_of(const pixvod_ctx* c) {
     s.lamR = inv_sq(c->P.sigma_R);
     s.lamN = inv_sq(c->P.sigma_N);
     s.lamD = inv_sq(c->P.sigma_D);
+    s.inv_sigD = 1.0 / (double)c->P.sigma_D;
     s.huber_k = c->P.huber_k;
     s.prior_ell = c->P.prior_log_depth;
     bool ident = true;

@@ -175,6 +175,47 @@ enum {
 int pixvod_profile_enable(pixvod_ctx* ctx, int enable);
 int pixvod_profile_read(pixvod_ctx* ctx, int kind, double* total_ms, int64_t* launches);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many independent sequences of mixed resolution advanced together.
+ * Every pass of the fused schedule is one launch over a work list of
+ * (sequence, tile) items; a frame step (frame preparation, prologue, n_iters
+ * passes, per-sequence reductions) is captured once as a HIP graph and
+ * replayed. Per-pixel arithmetic is the single-sequence code, so results are
+ * identical to per-sequence contexts and independent of the tile shape.
+ * All sequences share one parameter set and the fused schedule (damping 0).
+ */
+typedef struct pixvod_batch pixvod_batch;
+
+/* n >= 1 sequences with sizes H[i] x W[i] (>= 2) and intrinsics K[i]. */
+int pixvod_batch_create(int n, const int* H, const int* W, const pixvod_intrinsics* K,
+                        const pixvod_params* params, pixvod_batch** out_batch);
+int pixvod_batch_destroy(pixvod_batch* b);
+int pixvod_batch_set_stream(pixvod_batch* b, void* hip_stream);
+
+/* Keyframes for m listed sequences (seq_ids[k], images imgs[k], normals
+ * normals[k]), with the semantics of pixvod_set_keyframe. */
+int pixvod_batch_set_keyframes(pixvod_batch* b, int m, const int* seq_ids, const float* const* imgs,
+                               const float* const* normals, int where);
+
+/* One frame per sequence (frames[i], H[i]*W[i]); n_iters >= 1 iterations for
+ * all sequences; outs[i] receives sequence i's result (maps written when its
+ * pointers are set). Requires every sequence to have a keyframe. */
+int pixvod_batch_track(pixvod_batch* b, const float* const* frames, int where, int n_iters,
+                       pixvod_track_out* outs);
+
+/* Tile shape of the work list (tile_x * tile_y <= 256, both >= 1). */
+int pixvod_batch_set_tile(pixvod_batch* b, int tile_x, int tile_y);
+
+/* Times every candidate tile shape on n_iters passes over the current frames
+ * (the state is restored afterwards), selects the fastest and returns it. */
+int pixvod_batch_autotune(pixvod_batch* b, int n_iters, int* tile_x, int* tile_y);
+
+/* Average duration (ms) of the last frame step, timed with HIP events. */
+int pixvod_batch_last_step_ms(pixvod_batch* b, double* ms);
+
+/* Per-sequence state in the exchange layout of pixvod_get_state. */
+int pixvod_batch_get_state(pixvod_batch* b, int seq, void* dst, int where);
+
 /* Per-context message of the last failure; ctx == NULL gives the last
  * failure of a call that had no context (e.g. pixvod_create). */
 const char* pixvod_last_error(const pixvod_ctx* ctx);

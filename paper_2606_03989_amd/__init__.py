@@ -75,6 +75,17 @@ _SIGNATURES = {
     "pixvod_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "pixvod_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "pixvod_profile_read": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "pixvod_batch_create": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(Intrinsics),
+                                      C.POINTER(Params), C.POINTER(C.c_void_p)]),
+    "pixvod_batch_destroy": (C.c_int, [C.c_void_p]),
+    "pixvod_batch_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "pixvod_batch_set_keyframes": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_void_p),
+                                             C.POINTER(C.c_void_p), C.c_int]),
+    "pixvod_batch_track": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_int, C.c_int, C.POINTER(TrackOut)]),
+    "pixvod_batch_set_tile": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
+    "pixvod_batch_autotune": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "pixvod_batch_last_step_ms": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "pixvod_batch_get_state": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int]),
     "pixvod_last_error": (C.c_char_p, [C.c_void_p]),
     "pixvod_version": (C.c_char_p, []),
 }
@@ -226,6 +237,109 @@ class Tracker:
     def set_state(self, s):
         p, w, k = _ptr(s)
         _check(lib().pixvod_set_state(self._h, C.c_void_p(p), w), self._h)
+
+
+def _batch_check(rc: int, h=None):
+    if rc != OK:
+        msg = lib().pixvod_last_error(None)
+        raise PixvodError(rc, msg.decode() if msg else "")
+
+
+class Batch:
+    """Many independent sequences (mixed resolutions) advanced together; one
+    launch per pass over all sequences, frame steps replayed as HIP graphs."""
+
+    def __init__(self, shapes, Ks, params: Optional[Params] = None, **overrides):
+        self.shapes = [(int(h), int(w)) for h, w in shapes]
+        n = len(self.shapes)
+        if params is None:
+            params = default_params(**overrides)
+        self.params = params
+        Hs = (C.c_int * n)(*[h for h, _ in self.shapes])
+        Ws = (C.c_int * n)(*[w for _, w in self.shapes])
+        Kc = (Intrinsics * n)(*[Intrinsics(*[float(x) for x in k]) for k in Ks])
+        h = C.c_void_p()
+        _batch_check(lib().pixvod_batch_create(n, Hs, Ws, Kc, C.byref(params), C.byref(h)))
+        self._h = h
+        self.n = n
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pixvod_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream=None):
+        s = None if stream is None else C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else stream)
+        _batch_check(lib().pixvod_batch_set_stream(self._h, s))
+
+    def set_keyframes(self, seq_ids, imgs, normals):
+        m = len(seq_ids)
+        keep, pi, pn, where = [], [], [], None
+        for im, nm in zip(imgs, normals):
+            a, wa, ka = _ptr(im)
+            b, wb, kb = _ptr(nm)
+            if where is None:
+                where = wa
+            if wa != where or wb != where:
+                raise ValueError("all keyframe buffers must live in the same memory")
+            keep += [ka, kb]
+            pi.append(a)
+            pn.append(b)
+        ids = (C.c_int * m)(*seq_ids)
+        _batch_check(lib().pixvod_batch_set_keyframes(self._h, m, ids, (C.c_void_p * m)(*pi), (C.c_void_p * m)(*pn),
+                                                      HOST if where is None else where))
+
+    def set_tile(self, tx: int, ty: int):
+        _batch_check(lib().pixvod_batch_set_tile(self._h, int(tx), int(ty)))
+
+    def autotune(self, n_iters: int):
+        tx, ty = C.c_int(), C.c_int()
+        _batch_check(lib().pixvod_batch_autotune(self._h, int(n_iters), C.byref(tx), C.byref(ty)))
+        return tx.value, ty.value
+
+    def last_step_ms(self) -> float:
+        ms = C.c_double()
+        _batch_check(lib().pixvod_batch_last_step_ms(self._h, C.byref(ms)))
+        return ms.value
+
+    def track(self, frames, n_iters: int, maps: bool = False):
+        keep, ptrs, where = [], [], None
+        for f in frames:
+            p, w, k = _ptr(f)
+            if where is None:
+                where = w
+            if w != where:
+                raise ValueError("all frames must live in the same memory")
+            keep.append(k)
+            ptrs.append(p)
+        outs = (TrackOut * self.n)()
+        maps_out = []
+        for i, (H, W) in enumerate(self.shapes):
+            outs[i].out_where = HOST
+            if maps:
+                inv = np.empty((H, W), np.float32)
+                var = np.empty((H, W), np.float32)
+                outs[i].inv_depth, outs[i].inv_depth_var = inv.ctypes.data, var.ctypes.data
+                maps_out.append((inv, var))
+            else:
+                maps_out.append((None, None))
+        _batch_check(lib().pixvod_batch_track(self._h, (C.c_void_p * self.n)(*ptrs), where, int(n_iters), outs))
+        return [dict(xi=np.array(o.xi_rel[:]), T_world=np.array(o.T_world[:]).reshape(4, 4),
+                     valid_fraction=float(o.valid_fraction), frames_since_keyframe=int(o.frames_since_keyframe),
+                     flags=int(o.flags), inv_depth=mo[0], inv_depth_var=mo[1])
+                for o, mo in zip(outs, maps_out)]
+
+    def get_state(self, seq: int) -> np.ndarray:
+        H, W = self.shapes[seq]
+        s = np.empty((N_PLANES, H, W), np.float32)
+        _batch_check(lib().pixvod_batch_get_state(self._h, int(seq), C.c_void_p(s.ctypes.data), HOST))
+        return s
 
 
 def version() -> str:

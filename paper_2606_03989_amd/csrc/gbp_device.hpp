@@ -66,6 +66,38 @@ struct Inputs {
     const float* Gy;
 };
 
+// one sequence of a batch (device-resident descriptor)
+struct SeqDesc {
+    Geo g;
+    Inputs in;
+    float* X0;            // state ping-pong copies
+    float* X1;
+    float* var_ll;
+    float* valid;
+    const float* frame;   // staged dense target frame (H * W)
+    float* It;            // frame-prep outputs (same planes as in.It, in.Gx, in.Gy)
+    float* Gx;
+    float* Gy;
+    int tile_base;        // natural index of the sequence's first work item
+    int tiles_x;          // tiles per image row
+    int n_tiles;
+    int pad;
+};
+
+// arguments of the batched launches
+struct BatchLaunch {
+    const SeqDesc* seqs;  // device array, n_seq entries
+    const int2* work;     // device array: (natural item index, sequence) per workgroup
+    int n_work;
+    int n_seq;
+    int tile_x, tile_y;
+    int parity;           // buffer holding the canonical state
+    Strengths s;
+    int* health;
+    double* partial;      // 8 doubles per work item
+    double* result;       // 8 doubles per sequence
+};
+
 // ---------------------------------------------------------------------------
 // SE(3)
 

@@ -8,6 +8,8 @@ namespace pv {
 struct Geo;
 struct Strengths;
 struct Inputs;
+struct SeqDesc;
+struct BatchLaunch;
 
 hipError_t launch_frame_prep(const Geo& g, const float* src, long src_pitch, float* It, float* Gx, float* Gy,
                              hipStream_t st);
@@ -29,5 +31,11 @@ hipError_t launch_outputs(const Geo& g, const float* X, const float* var_ll, int
                           float* inv_var, hipStream_t st);
 hipError_t launch_pack_state(const Geo& g, const float* X, float* dense, int to_dense, hipStream_t st);
 hipError_t launch_copy_plane(const Geo& g, const float* dense, float* plane, hipStream_t st);
+
+// one frame step of a batch: clear health, frame prep, prologue, n passes,
+// per-sequence statistics (canonical state ends in buffer parity ^ (n > 0 ? (n + 1) & 1 : 0))
+hipError_t launch_batch_frame_step(const BatchLaunch& b, int n_iters, hipStream_t st);
+// bare passes (autotuning and timing)
+hipError_t launch_batch_passes(const BatchLaunch& b, int n_iters, bool prologue, bool final_last, hipStream_t st);
 
 }  // namespace pv

@@ -245,11 +245,9 @@ __device__ inline void round_point(double tau[6], double& ell) {
 // frame and keyframe preparation
 
 // central differences inside, one-sided at the border (row a1)
-__global__ void k_frame_prep(Geo g, const float* __restrict__ src, long src_pitch, float* __restrict__ It,
-                             float* __restrict__ Gx, float* __restrict__ Gy) {
-    const int u = blockIdx.x * blockDim.x + threadIdx.x;
-    const int v = blockIdx.y * blockDim.y + threadIdx.y;
-    if (u >= g.W || v >= g.H) return;
+__device__ __attribute__((always_inline)) inline void frame_prep_pixel(const Geo& g, const float* __restrict__ src, long src_pitch,
+                                        float* __restrict__ It, float* __restrict__ Gx, float* __restrict__ Gy,
+                                        int u, int v) {
     const float* row = src + (long)v * src_pitch;
     const float c = row[u];
     float gx, gy;
@@ -263,6 +261,14 @@ __global__ void k_frame_prep(Geo g, const float* __restrict__ src, long src_pitc
     It[p] = c;
     Gx[p] = gx;
     Gy[p] = gy;
+}
+
+__global__ void k_frame_prep(Geo g, const float* __restrict__ src, long src_pitch, float* __restrict__ It,
+                             float* __restrict__ Gx, float* __restrict__ Gy) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y * blockDim.y + threadIdx.y;
+    if (u >= g.W || v >= g.H) return;
+    frame_prep_pixel(g, src, src_pitch, It, Gx, Gy, u, v);
 }
 
 // keyframe image, normal-integration targets (row a2) and the state reset:
@@ -453,12 +459,9 @@ __global__ __launch_bounds__(256) void k_pf_update(Geo g, Strengths s, Inputs in
 // ---------------------------------------------------------------------------
 // fused schedule
 
-// prologue: belief of the canonical state and the first partials
-__global__ __launch_bounds__(256) void k_fu_prologue(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
-                                                     float* __restrict__ Y, int* __restrict__ health) {
-    const int u = blockIdx.x * blockDim.x + threadIdx.x;
-    const int v = blockIdx.y * blockDim.y + threadIdx.y;
-    if (u >= g.W || v >= g.H) return;
+// prologue of one pixel: belief of the canonical state and the first partials
+__device__ __attribute__((always_inline)) inline void prologue_pixel(const Geo& g, const Strengths& s, const Inputs& in, const float* __restrict__ X,
+                                      float* __restrict__ Y, int* __restrict__ health, int u, int v) {
     const long p = pix_of(g, u, v);
     double tau[6], ell, R[9], t[3], L[28], eta[7];
     load_point(X, g, p, tau, ell);
@@ -473,15 +476,13 @@ __global__ __launch_bounds__(256) void k_fu_prologue(Geo g, Strengths s, Inputs 
     if (!ok) atomicOr(health, 1);
 }
 
-// one iteration: complete, update, relinearise, then (not FINAL) emit the
-// next partials or (FINAL) write the canonical state and per-pixel outputs
+// one iteration of one pixel: complete, update, relinearise, then (not
+// FINAL) emit the next partials or (FINAL) write the canonical state and the
+// per-pixel outputs
 template <bool FINAL>
-__global__ __launch_bounds__(256) void k_fu_iterate(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
-                                                    float* __restrict__ Y, float* __restrict__ var_ll,
-                                                    float* __restrict__ valid, int* __restrict__ health) {
-    const int u = blockIdx.x * blockDim.x + threadIdx.x;
-    const int v = blockIdx.y * blockDim.y + threadIdx.y;
-    if (u >= g.W || v >= g.H) return;
+__device__ __attribute__((always_inline)) inline void iterate_pixel(const Geo& g, const Strengths& s, const Inputs& in, const float* __restrict__ X,
+                                     float* __restrict__ Y, float* __restrict__ var_ll, float* __restrict__ valid,
+                                     int* __restrict__ health, int u, int v) {
     const long p = pix_of(g, u, v);
     double tau[6], ell, R[9], t[3], L[28], eta[7];
     load_point(X, g, p, tau, ell);
@@ -504,6 +505,24 @@ __global__ __launch_bounds__(256) void k_fu_iterate(Geo g, Strengths s, Inputs i
         emit_partials(g, s, in, u, v, L, eta, mid, mn, Y, ok);
     }
     if (!ok) atomicOr(health, 1);
+}
+
+__global__ __launch_bounds__(256) void k_fu_prologue(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
+                                                     float* __restrict__ Y, int* __restrict__ health) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y * blockDim.y + threadIdx.y;
+    if (u >= g.W || v >= g.H) return;
+    prologue_pixel(g, s, in, X, Y, health, u, v);
+}
+
+template <bool FINAL>
+__global__ __launch_bounds__(256) void k_fu_iterate(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
+                                                    float* __restrict__ Y, float* __restrict__ var_ll,
+                                                    float* __restrict__ valid, int* __restrict__ health) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y * blockDim.y + threadIdx.y;
+    if (u >= g.W || v >= g.H) return;
+    iterate_pixel<FINAL>(g, s, in, X, Y, var_ll, valid, health, u, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -596,6 +615,155 @@ __global__ void k_copy_plane(Geo g, const float* __restrict__ dense, float* __re
     const int v = blockIdx.y * blockDim.y + threadIdx.y;
     if (u >= g.W || v >= g.H) return;
     plane[pix_of(g, u, v)] = dense[(long)v * g.W + u];
+}
+
+// ---------------------------------------------------------------------------
+// batched schedule: many sequences of mixed resolution in one launch per pass.
+// Each workgroup takes one (sequence, tile) item of the work list; the
+// per-pixel arithmetic is the single-sequence code, so results do not depend
+// on batching or on the tile shape.
+
+__device__ inline bool batch_pixel(const SeqDesc* __restrict__ seqs, const int2* __restrict__ work,
+                                   const SeqDesc*& d, int& u, int& v, int& item) {
+    const int2 w = work[blockIdx.x];
+    item = w.x;
+    d = &seqs[w.y];
+    const int tile = w.x - d->tile_base;
+    u = (tile % d->tiles_x) * (int)blockDim.x + (int)threadIdx.x;
+    v = (tile / d->tiles_x) * (int)blockDim.y + (int)threadIdx.y;
+    return u < d->g.W && v < d->g.H;
+}
+
+__global__ void k_batch_frame_prep(const SeqDesc* __restrict__ seqs, const int2* __restrict__ work) {
+    const SeqDesc* d;
+    int u, v, item;
+    if (!batch_pixel(seqs, work, d, u, v, item)) return;
+    frame_prep_pixel(d->g, d->frame, d->g.W, d->It, d->Gx, d->Gy, u, v);
+}
+
+__global__ __launch_bounds__(256) void k_batch_prologue(const SeqDesc* __restrict__ seqs, const int2* __restrict__ work,
+                                                        int parity, Strengths s, int* __restrict__ health) {
+    const SeqDesc* d;
+    int u, v, item;
+    if (!batch_pixel(seqs, work, d, u, v, item)) return;
+    const float* X = parity ? d->X1 : d->X0;
+    float* Y = parity ? d->X0 : d->X1;
+    prologue_pixel(d->g, s, d->in, X, Y, health, u, v);
+}
+
+template <bool FINAL>
+__global__ __launch_bounds__(256) void k_batch_iterate(const SeqDesc* __restrict__ seqs, const int2* __restrict__ work,
+                                                       int parity, Strengths s, int* __restrict__ health) {
+    const SeqDesc* d;
+    int u, v, item;
+    if (!batch_pixel(seqs, work, d, u, v, item)) return;
+    const float* X = parity ? d->X1 : d->X0;
+    float* Y = parity ? d->X0 : d->X1;
+    iterate_pixel<FINAL>(d->g, s, d->in, X, Y, d->var_ll, d->valid, health, u, v);
+}
+
+// per work item: sum of the six pose planes, valid count, non-finite count of
+// the tile, written at the item's natural index (fixed-order reduction)
+__global__ __launch_bounds__(256) void k_batch_stats(const SeqDesc* __restrict__ seqs, const int2* __restrict__ work,
+                                                     int parity, double* __restrict__ partial) {
+    __shared__ double sh[8][256];
+    const SeqDesc* d;
+    int u, v, item;
+    const bool in_img = batch_pixel(seqs, work, d, u, v, item);
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (in_img) {
+        const float* X = parity ? d->X1 : d->X0;
+        const long p = pix_of(d->g, u, v);
+        bool fin = true;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const float x = X[(long)k * d->g.plane + p];
+            acc[k] = (double)x;
+            fin = fin && isfinite(x);
+        }
+        fin = fin && isfinite(X[(long)P_ELL * d->g.plane + p]);
+        acc[6] = (double)d->valid[p];
+        acc[7] = fin ? 0.0 : 1.0;
+    }
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const int nt = blockDim.x * blockDim.y;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sh[k][tid] = acc[k];
+    for (int k = nt; k < 256; k += nt)
+        if (tid + k < 256)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) sh[c][tid + k] = 0.0;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) sh[k][tid] += sh[k][tid + w];
+        __syncthreads();
+    }
+    if (tid < 8) partial[(long)item * 8 + tid] = sh[tid][0];
+}
+
+// one block per sequence: sums its tiles' partials in order
+__global__ __launch_bounds__(256) void k_batch_final(const SeqDesc* __restrict__ seqs, const double* __restrict__ partial,
+                                                     double* __restrict__ result) {
+    __shared__ double sh[8][256];
+    const SeqDesc& d = seqs[blockIdx.x];
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int t = threadIdx.x; t < d.n_tiles; t += 256)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] += partial[(long)(d.tile_base + t) * 8 + k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sh[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 8) result[(long)blockIdx.x * 8 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void k_clear_int(int* __restrict__ p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = 0;
+}
+
+hipError_t launch_batch_frame_step(const BatchLaunch& b, int n_iters, hipStream_t st) {
+    const dim3 blk(b.tile_x, b.tile_y), grid(b.n_work);
+    hipLaunchKernelGGL(k_clear_int, dim3(1), dim3(64), 0, st, b.health);
+    hipLaunchKernelGGL(k_batch_frame_prep, grid, blk, 0, st, b.seqs, b.work);
+    int parity = b.parity;
+    if (n_iters > 0) {
+        hipLaunchKernelGGL(k_batch_prologue, grid, blk, 0, st, b.seqs, b.work, parity, b.s, b.health);
+        parity ^= 1;
+        for (int it = 0; it < n_iters; ++it) {
+            if (it == n_iters - 1)
+                hipLaunchKernelGGL(k_batch_iterate<true>, grid, blk, 0, st, b.seqs, b.work, parity, b.s, b.health);
+            else
+                hipLaunchKernelGGL(k_batch_iterate<false>, grid, blk, 0, st, b.seqs, b.work, parity, b.s, b.health);
+            parity ^= 1;
+        }
+    }
+    hipLaunchKernelGGL(k_batch_stats, grid, blk, 0, st, b.seqs, b.work, parity, b.partial);
+    hipLaunchKernelGGL(k_batch_final, dim3(b.n_seq), dim3(256), 0, st, b.seqs, b.partial, b.result);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_passes(const BatchLaunch& b, int n_iters, bool prologue, bool final_last, hipStream_t st) {
+    const dim3 blk(b.tile_x, b.tile_y), grid(b.n_work);
+    int parity = b.parity;
+    if (prologue) {
+        hipLaunchKernelGGL(k_batch_prologue, grid, blk, 0, st, b.seqs, b.work, parity, b.s, b.health);
+        parity ^= 1;
+    }
+    for (int it = 0; it < n_iters; ++it) {
+        if (final_last && it == n_iters - 1)
+            hipLaunchKernelGGL(k_batch_iterate<true>, grid, blk, 0, st, b.seqs, b.work, parity, b.s, b.health);
+        else
+            hipLaunchKernelGGL(k_batch_iterate<false>, grid, blk, 0, st, b.seqs, b.work, parity, b.s, b.health);
+        parity ^= 1;
+    }
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

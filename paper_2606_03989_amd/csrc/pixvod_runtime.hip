@@ -634,3 +634,512 @@ int pixvod_set_state(pixvod_ctx* c, const void* src, int where) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batches
+
+namespace {
+
+struct BatchSeq {
+    int H = 0, W = 0, pitch = 0;
+    long plane = 0;
+    pixvod_intrinsics K{};
+    float* X[2] = {nullptr, nullptr};
+    float *Is = nullptr, *cxt = nullptr, *cyt = nullptr, *sig = nullptr;
+    float *It = nullptr, *Gx = nullptr, *Gy = nullptr, *var_ll = nullptr, *valid = nullptr;
+    float *frame = nullptr, *kf_stage = nullptr, *out_stage = nullptr, *dense = nullptr;
+    bool have_kf = false, have_track = false;
+    double T_w_kf[16];
+    double xi_last[6];
+    int frames_since_kf = 0;
+};
+
+}  // namespace
+
+struct pixvod_batch {
+    int n = 0;
+    pixvod_params P{};
+    hipStream_t own_stream = nullptr, stream = nullptr;
+    std::vector<BatchSeq> seq;
+    SeqDesc* d_seqs = nullptr;
+    int2* d_work = nullptr;
+    int n_work = 0, tile_x = 64, tile_y = 4;
+    double *d_partial = nullptr, *d_result = nullptr, *h_result = nullptr;
+    int *d_health = nullptr, *h_health = nullptr;
+    int parity = 0;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    int graph_iters = -1;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double last_ms = 0.0;
+    std::string err;
+};
+
+static int bfail(pixvod_batch* b, int code, const std::string& msg) {
+    if (b) b->err = msg;
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY_B(b, expr)                                                                    \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return bfail((b), PIXVOD_EHIP, std::string(#expr ": ") + hipGetErrorString(e_));  \
+    } while (0)
+
+static Geo geo_of_seq(const BatchSeq& q) {
+    Geo g;
+    g.H = q.H;
+    g.W = q.W;
+    g.pitch = q.pitch;
+    g.plane = q.plane;
+    g.fx = q.K.fx;
+    g.fy = q.K.fy;
+    g.cx = q.K.cx;
+    g.cy = q.K.cy;
+    return g;
+}
+
+static Strengths strengths_of_params(const pixvod_params& P) {
+    pixvod_ctx tmp;
+    tmp.P = P;
+    tmp.has_sigma = false;
+    return strengths_of(&tmp);
+}
+
+static void batch_drop_graphs(pixvod_batch* b) {
+    for (int k = 0; k < 2; ++k) {
+        if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
+        if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
+        b->exec[k] = nullptr;
+        b->graph[k] = nullptr;
+    }
+    b->graph_iters = -1;
+}
+
+static void batch_release(pixvod_batch* b) {
+    batch_drop_graphs(b);
+    for (auto& q : b->seq) {
+        void* bufs[] = {q.X[0], q.X[1], q.Is, q.cxt, q.cyt, q.sig, q.It, q.Gx, q.Gy, q.var_ll, q.valid,
+                        q.frame, q.kf_stage, q.out_stage, q.dense};
+        for (void* p : bufs)
+            if (p) (void)hipFree(p);
+    }
+    void* bufs[] = {b->d_seqs, b->d_work, b->d_partial, b->d_result, b->d_health};
+    for (void* p : bufs)
+        if (p) (void)hipFree(p);
+    if (b->h_result) (void)hipHostFree(b->h_result);
+    if (b->h_health) (void)hipHostFree(b->h_health);
+    if (b->ev0) (void)hipEventDestroy(b->ev0);
+    if (b->ev1) (void)hipEventDestroy(b->ev1);
+    if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
+}
+
+// work list for the current tile shape: natural order is sequence-major,
+// row-major tiles; workgroup w runs natural item perm(w) so that the
+// workgroups dispatched to one XCD (w mod 8) cover a contiguous range
+static int batch_build_work(pixvod_batch* b) {
+    std::vector<SeqDesc> descs(b->n);
+    int total = 0;
+    for (int i = 0; i < b->n; ++i) {
+        BatchSeq& q = b->seq[i];
+        SeqDesc& d = descs[i];
+        std::memset(&d, 0, sizeof(d));
+        d.g = geo_of_seq(q);
+        d.in.Is = q.Is;
+        d.in.cxt = q.cxt;
+        d.in.cyt = q.cyt;
+        d.in.sigD = q.sig;
+        d.in.It = q.It;
+        d.in.Gx = q.Gx;
+        d.in.Gy = q.Gy;
+        d.X0 = q.X[0];
+        d.X1 = q.X[1];
+        d.var_ll = q.var_ll;
+        d.valid = q.valid;
+        d.frame = q.frame;
+        d.It = q.It;
+        d.Gx = q.Gx;
+        d.Gy = q.Gy;
+        d.tiles_x = (q.W + b->tile_x - 1) / b->tile_x;
+        const int ty = (q.H + b->tile_y - 1) / b->tile_y;
+        d.n_tiles = d.tiles_x * ty;
+        d.tile_base = total;
+        total += d.n_tiles;
+    }
+    std::vector<int2> natural(total);
+    for (int i = 0; i < b->n; ++i)
+        for (int t = 0; t < descs[i].n_tiles; ++t) natural[descs[i].tile_base + t] = make_int2(descs[i].tile_base + t, i);
+    const int X = 8;
+    std::vector<int> start(X + 1, 0);
+    for (int x = 0; x < X; ++x) start[x + 1] = start[x] + (total - x + X - 1) / X;
+    std::vector<int2> work(total);
+    for (int w = 0; w < total; ++w) work[w] = natural[start[w % X] + w / X];
+    if (b->d_work) (void)hipFree(b->d_work);
+    if (b->d_partial) (void)hipFree(b->d_partial);
+    b->d_work = nullptr;
+    b->d_partial = nullptr;
+    if (hipMalloc((void**)&b->d_work, sizeof(int2) * total) != hipSuccess ||
+        hipMalloc((void**)&b->d_partial, sizeof(double) * 8 * total) != hipSuccess)
+        return bfail(b, PIXVOD_ENOMEM, "work list allocation failed");
+    HIP_TRY_B(b, hipMemcpy(b->d_work, work.data(), sizeof(int2) * total, hipMemcpyHostToDevice));
+    HIP_TRY_B(b, hipMemcpy(b->d_seqs, descs.data(), sizeof(SeqDesc) * b->n, hipMemcpyHostToDevice));
+    b->n_work = total;
+    batch_drop_graphs(b);
+    return PIXVOD_OK;
+}
+
+static BatchLaunch batch_launch_args(const pixvod_batch* b) {
+    BatchLaunch L;
+    L.seqs = b->d_seqs;
+    L.work = b->d_work;
+    L.n_work = b->n_work;
+    L.n_seq = b->n;
+    L.tile_x = b->tile_x;
+    L.tile_y = b->tile_y;
+    L.parity = b->parity;
+    L.s = strengths_of_params(b->P);
+    L.health = b->d_health;
+    L.partial = b->d_partial;
+    L.result = b->d_result;
+    return L;
+}
+
+extern "C" {
+
+int pixvod_batch_create(int n, const int* H, const int* W, const pixvod_intrinsics* K, const pixvod_params* params,
+                        pixvod_batch** out) {
+    if (!out) return bfail(nullptr, PIXVOD_EINVAL, "out_batch is NULL");
+    *out = nullptr;
+    if (n < 1 || !H || !W || !K) return bfail(nullptr, PIXVOD_EINVAL, "need n >= 1 and H, W, K arrays");
+    long total = 0;
+    for (int i = 0; i < n; ++i) {
+        if (H[i] < 2 || W[i] < 2) return bfail(nullptr, PIXVOD_EINVAL, "H and W must be >= 2");
+        if (!(K[i].fx > 0) || !(K[i].fy > 0) || !std::isfinite(K[i].cx) || !std::isfinite(K[i].cy))
+            return bfail(nullptr, PIXVOD_EINVAL, "intrinsics must be finite with fx, fy > 0");
+        total += (long)H[i] * W[i];
+    }
+    if (total > (1L << 30)) return bfail(nullptr, PIXVOD_EINVAL, "batch too large");
+    pixvod_params P;
+    if (params) P = *params;
+    else pixvod_default_params(&P);
+    if (!finite_params(&P)) return bfail(nullptr, PIXVOD_EINVAL, "invalid parameters");
+    if (P.damping != 0.0f) return bfail(nullptr, PIXVOD_EINVAL, "batches use the fused schedule (damping 0)");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+        return bfail(nullptr, PIXVOD_ENODEV, "no HIP device available");
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+        std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return bfail(nullptr, PIXVOD_ENODEV, "need a gfx950 device");
+
+    pixvod_batch* b = new pixvod_batch();
+    b->n = n;
+    b->P = P;
+    b->seq.resize(n);
+    int rc = PIXVOD_OK;
+    auto alloc = [&](float** p, size_t cnt) {
+        if (rc) return;
+        if (hipMalloc((void**)p, cnt * sizeof(float)) != hipSuccess) {
+            *p = nullptr;
+            rc = PIXVOD_ENOMEM;
+        }
+    };
+    for (int i = 0; i < n && !rc; ++i) {
+        BatchSeq& q = b->seq[i];
+        q.H = H[i];
+        q.W = W[i];
+        q.pitch = (W[i] + 63) / 64 * 64;
+        q.plane = (long)q.H * q.pitch;
+        q.K = K[i];
+        std::memset(q.T_w_kf, 0, sizeof(q.T_w_kf));
+        for (int k = 0; k < 4; ++k) q.T_w_kf[k * 5] = 1.0;
+        std::memset(q.xi_last, 0, sizeof(q.xi_last));
+        const size_t pl = (size_t)q.plane, N = (size_t)q.H * q.W;
+        alloc(&q.X[0], pl * N_PLANES);
+        alloc(&q.X[1], pl * N_PLANES);
+        float** planes[] = {&q.Is, &q.cxt, &q.cyt, &q.sig, &q.It, &q.Gx, &q.Gy, &q.var_ll, &q.valid};
+        for (float** p : planes) alloc(p, pl);
+        alloc(&q.frame, N);
+        alloc(&q.kf_stage, 4 * N);
+        alloc(&q.out_stage, 2 * N);
+    }
+    if (!rc && hipMalloc((void**)&b->d_seqs, sizeof(SeqDesc) * n) != hipSuccess) rc = PIXVOD_ENOMEM;
+    if (!rc && hipMalloc((void**)&b->d_result, sizeof(double) * 8 * n) != hipSuccess) rc = PIXVOD_ENOMEM;
+    if (!rc && hipMalloc((void**)&b->d_health, sizeof(int)) != hipSuccess) rc = PIXVOD_ENOMEM;
+    if (!rc && hipHostMalloc((void**)&b->h_result, sizeof(double) * 8 * n) != hipSuccess) rc = PIXVOD_ENOMEM;
+    if (!rc && hipHostMalloc((void**)&b->h_health, sizeof(int)) != hipSuccess) rc = PIXVOD_ENOMEM;
+    if (!rc && hipStreamCreateWithFlags(&b->own_stream, hipStreamNonBlocking) != hipSuccess) rc = PIXVOD_EHIP;
+    if (!rc && (hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess)) rc = PIXVOD_EHIP;
+    if (!rc) rc = batch_build_work(b);
+    if (!rc) {
+        const float ell0 = (float)(-std::log((double)P.init_inv_depth));
+        for (auto& q : b->seq) {
+            const Geo g = geo_of_seq(q);
+            if (launch_init_state(g, q.X[0], ell0, b->own_stream) != hipSuccess ||
+                launch_init_state(g, q.X[1], ell0, b->own_stream) != hipSuccess ||
+                hipMemsetAsync(q.var_ll, 0, (size_t)q.plane * sizeof(float), b->own_stream) != hipSuccess) {
+                rc = PIXVOD_EHIP;
+                break;
+            }
+        }
+        if (!rc && hipStreamSynchronize(b->own_stream) != hipSuccess) rc = PIXVOD_EHIP;
+    }
+    if (rc) {
+        std::string m = b->err.empty() ? "batch allocation failed" : b->err;
+        batch_release(b);
+        delete b;
+        return bfail(nullptr, rc, m);
+    }
+    b->stream = b->own_stream;
+    *out = b;
+    return PIXVOD_OK;
+}
+
+int pixvod_batch_destroy(pixvod_batch* b) {
+    if (!b) return PIXVOD_OK;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    batch_release(b);
+    delete b;
+    return PIXVOD_OK;
+}
+
+int pixvod_batch_set_stream(pixvod_batch* b, void* s) {
+    if (!b) return bfail(nullptr, PIXVOD_EINVAL, "batch is NULL");
+    HIP_TRY_B(b, hipStreamSynchronize(b->stream));
+    b->stream = s ? (hipStream_t)s : b->own_stream;
+    batch_drop_graphs(b);
+    return PIXVOD_OK;
+}
+
+int pixvod_batch_set_keyframes(pixvod_batch* b, int m, const int* ids, const float* const* imgs,
+                               const float* const* normals, int where) {
+    if (!b) return bfail(nullptr, PIXVOD_EINVAL, "batch is NULL");
+    if (m < 0 || (m > 0 && (!ids || !imgs || !normals))) return bfail(b, PIXVOD_EINVAL, "bad keyframe list");
+    if (where != PIXVOD_HOST && where != PIXVOD_DEVICE) return bfail(b, PIXVOD_EINVAL, "bad location");
+    for (int k = 0; k < m; ++k)
+        if (ids[k] < 0 || ids[k] >= b->n || !imgs[k] || !normals[k])
+            return bfail(b, PIXVOD_EINVAL, "bad keyframe entry");
+    for (int k = 0; k < m; ++k) {
+        BatchSeq& q = b->seq[ids[k]];
+        const size_t N = (size_t)q.H * q.W;
+        const float *di = imgs[k], *dn = normals[k];
+        if (where == PIXVOD_HOST) {
+            HIP_TRY_B(b, hipMemcpyAsync(q.kf_stage, imgs[k], N * sizeof(float), hipMemcpyHostToDevice, b->stream));
+            HIP_TRY_B(b, hipMemcpyAsync(q.kf_stage + N, normals[k], 3 * N * sizeof(float), hipMemcpyHostToDevice,
+                                        b->stream));
+            di = q.kf_stage;
+            dn = q.kf_stage + N;
+        }
+        HIP_TRY_B(b, launch_keyframe_prep(geo_of_seq(q), di, dn, q.Is, q.cxt, q.cyt, q.X[b->parity],
+                                          q.X[1 - b->parity], b->stream));
+        if (q.have_track) {
+            double E[16], Ei[16], Tw[16];
+            host_se3_exp(q.xi_last, E);
+            host_se3_inverse(E, Ei);
+            host_mat4_mul(q.T_w_kf, Ei, Tw);
+            std::memcpy(q.T_w_kf, Tw, sizeof(Tw));
+        }
+        std::memset(q.xi_last, 0, sizeof(q.xi_last));
+        q.have_track = false;
+        q.have_kf = true;
+        q.frames_since_kf = 0;
+    }
+    HIP_TRY_B(b, hipStreamSynchronize(b->stream));
+    return PIXVOD_OK;
+}
+
+int pixvod_batch_set_tile(pixvod_batch* b, int tx, int ty) {
+    if (!b) return bfail(nullptr, PIXVOD_EINVAL, "batch is NULL");
+    if (tx < 1 || ty < 1 || tx * ty > 256) return bfail(b, PIXVOD_EINVAL, "tile must have 1..256 threads");
+    HIP_TRY_B(b, hipStreamSynchronize(b->stream));
+    b->tile_x = tx;
+    b->tile_y = ty;
+    return batch_build_work(b);
+}
+
+// graph of one frame step for the current parity
+static int batch_graph(pixvod_batch* b, int n_iters, hipGraphExec_t* exec) {
+    if (b->graph_iters != n_iters) batch_drop_graphs(b);
+    const int k = b->parity;
+    if (!b->exec[k]) {
+        const BatchLaunch L = batch_launch_args(b);
+        HIP_TRY_B(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t le = launch_batch_frame_step(L, n_iters, b->stream);
+        hipGraph_t g = nullptr;
+        hipError_t ce = hipStreamEndCapture(b->stream, &g);
+        if (le != hipSuccess || ce != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return bfail(b, PIXVOD_EHIP, std::string("graph capture failed: ") +
+                                             hipGetErrorString(le != hipSuccess ? le : ce));
+        }
+        b->graph[k] = g;
+        HIP_TRY_B(b, hipGraphInstantiate(&b->exec[k], g, nullptr, nullptr, 0));
+        b->graph_iters = n_iters;
+    }
+    *exec = b->exec[k];
+    return PIXVOD_OK;
+}
+
+int pixvod_batch_track(pixvod_batch* b, const float* const* frames, int where, int n_iters, pixvod_track_out* outs) {
+    if (!b) return bfail(nullptr, PIXVOD_EINVAL, "batch is NULL");
+    if (!frames || !outs) return bfail(b, PIXVOD_EINVAL, "frames and outs are required");
+    if (where != PIXVOD_HOST && where != PIXVOD_DEVICE) return bfail(b, PIXVOD_EINVAL, "bad location");
+    if (n_iters < 1) return bfail(b, PIXVOD_EINVAL, "n_iters must be >= 1");
+    for (int i = 0; i < b->n; ++i) {
+        if (!frames[i]) return bfail(b, PIXVOD_EINVAL, "missing frame");
+        if (outs[i].out_where != PIXVOD_HOST && outs[i].out_where != PIXVOD_DEVICE)
+            return bfail(b, PIXVOD_EINVAL, "bad output location");
+        if (!b->seq[i].have_kf) return bfail(b, PIXVOD_ESTATE, "a sequence has no keyframe");
+    }
+    for (int i = 0; i < b->n; ++i) {
+        BatchSeq& q = b->seq[i];
+        const size_t N = (size_t)q.H * q.W;
+        HIP_TRY_B(b, hipMemcpyAsync(q.frame, frames[i], N * sizeof(float),
+                                    where == PIXVOD_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                                    b->stream));
+    }
+    hipGraphExec_t exec = nullptr;
+    int rc = batch_graph(b, n_iters, &exec);
+    if (rc) return rc;
+    HIP_TRY_B(b, hipEventRecord(b->ev0, b->stream));
+    HIP_TRY_B(b, hipGraphLaunch(exec, b->stream));
+    HIP_TRY_B(b, hipEventRecord(b->ev1, b->stream));
+    b->parity ^= (n_iters + 1) & 1;
+    HIP_TRY_B(b, hipMemcpyAsync(b->h_result, b->d_result, sizeof(double) * 8 * b->n, hipMemcpyDeviceToHost,
+                                b->stream));
+    HIP_TRY_B(b, hipMemcpyAsync(b->h_health, b->d_health, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+    for (int i = 0; i < b->n; ++i) {
+        BatchSeq& q = b->seq[i];
+        pixvod_track_out* o = &outs[i];
+        if (!o->inv_depth && !o->inv_depth_var) continue;
+        const size_t N = (size_t)q.H * q.W;
+        float* di = o->inv_depth;
+        float* dv = o->inv_depth_var;
+        if (o->out_where == PIXVOD_HOST) {
+            di = o->inv_depth ? q.out_stage : nullptr;
+            dv = o->inv_depth_var ? q.out_stage + N : nullptr;
+        }
+        HIP_TRY_B(b, launch_outputs(geo_of_seq(q), q.X[b->parity], q.var_ll, 1, di, dv, b->stream));
+        if (o->out_where == PIXVOD_HOST) {
+            if (o->inv_depth)
+                HIP_TRY_B(b, hipMemcpyAsync(o->inv_depth, q.out_stage, N * sizeof(float), hipMemcpyDeviceToHost,
+                                            b->stream));
+            if (o->inv_depth_var)
+                HIP_TRY_B(b, hipMemcpyAsync(o->inv_depth_var, q.out_stage + N, N * sizeof(float),
+                                            hipMemcpyDeviceToHost, b->stream));
+        }
+    }
+    HIP_TRY_B(b, hipStreamSynchronize(b->stream));
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, b->ev0, b->ev1) == hipSuccess) b->last_ms = ms;
+    for (int i = 0; i < b->n; ++i) {
+        BatchSeq& q = b->seq[i];
+        pixvod_track_out* o = &outs[i];
+        const double inv_n = 1.0 / ((double)q.H * q.W);
+        for (int k = 0; k < 6; ++k) {
+            q.xi_last[k] = b->h_result[8 * i + k] * inv_n;
+            o->xi_rel[k] = q.xi_last[k];
+        }
+        q.have_track = true;
+        q.frames_since_kf += 1;
+        double E[16], Ei[16];
+        host_se3_exp(q.xi_last, E);
+        host_se3_inverse(E, Ei);
+        host_mat4_mul(q.T_w_kf, Ei, o->T_world);
+        const float vf = (float)(b->h_result[8 * i + 6] * inv_n);
+        o->valid_fraction = vf;
+        o->frames_since_keyframe = q.frames_since_kf;
+        unsigned f = 0;
+        if (q.frames_since_kf >= b->P.kf_max_frames || vf < b->P.kf_min_valid_frac) f |= PIXVOD_KEYFRAME_DUE;
+        if (vf < b->P.kf_min_valid_frac) f |= PIXVOD_LOW_OVERLAP;
+        if (b->h_result[8 * i + 7] > 0.0 || *b->h_health != 0) f |= PIXVOD_DIVERGED;
+        o->flags = f;
+    }
+    return PIXVOD_OK;
+}
+
+int pixvod_batch_last_step_ms(pixvod_batch* b, double* ms) {
+    if (!b || !ms) return bfail(b, PIXVOD_EINVAL, "batch and ms are required");
+    *ms = b->last_ms;
+    return PIXVOD_OK;
+}
+
+int pixvod_batch_get_state(pixvod_batch* b, int seq, void* dst, int where) {
+    if (!b) return bfail(nullptr, PIXVOD_EINVAL, "batch is NULL");
+    if (seq < 0 || seq >= b->n || !dst) return bfail(b, PIXVOD_EINVAL, "bad sequence or destination");
+    if (where != PIXVOD_HOST && where != PIXVOD_DEVICE) return bfail(b, PIXVOD_EINVAL, "bad location");
+    BatchSeq& q = b->seq[seq];
+    const size_t n = (size_t)N_PLANES * q.H * q.W;
+    float* d = (float*)dst;
+    if (where == PIXVOD_HOST) {
+        if (!q.dense && hipMalloc((void**)&q.dense, n * sizeof(float)) != hipSuccess)
+            return bfail(b, PIXVOD_ENOMEM, "staging allocation failed");
+        d = q.dense;
+    }
+    HIP_TRY_B(b, launch_pack_state(geo_of_seq(q), q.X[b->parity], d, 1, b->stream));
+    if (where == PIXVOD_HOST) HIP_TRY_B(b, hipMemcpyAsync(dst, d, n * sizeof(float), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY_B(b, hipStreamSynchronize(b->stream));
+    return PIXVOD_OK;
+}
+
+int pixvod_batch_autotune(pixvod_batch* b, int n_iters, int* tx_out, int* ty_out) {
+    if (!b) return bfail(nullptr, PIXVOD_EINVAL, "batch is NULL");
+    if (n_iters < 1 || !tx_out || !ty_out) return bfail(b, PIXVOD_EINVAL, "bad autotune arguments");
+    for (auto& q : b->seq)
+        if (!q.have_kf) return bfail(b, PIXVOD_ESTATE, "a sequence has no keyframe");
+    static const int cand[][2] = {{64, 1}, {64, 2}, {64, 4}, {128, 1}, {128, 2}, {256, 1}, {32, 4}, {32, 8}, {16, 16}};
+    // snapshot of both state copies; the passes below run on the live buffers
+    std::vector<float*> snap(2 * b->n, nullptr);
+    for (int i = 0; i < b->n && true; ++i)
+        for (int k = 0; k < 2; ++k) {
+            const size_t bytes = (size_t)b->seq[i].plane * N_PLANES * sizeof(float);
+            if (hipMalloc((void**)&snap[2 * i + k], bytes) != hipSuccess) {
+                for (float* p : snap)
+                    if (p) (void)hipFree(p);
+                return bfail(b, PIXVOD_ENOMEM, "autotune snapshot allocation failed");
+            }
+            HIP_TRY_B(b, hipMemcpyAsync(snap[2 * i + k], b->seq[i].X[k], bytes, hipMemcpyDeviceToDevice, b->stream));
+        }
+    const int tx0 = b->tile_x, ty0 = b->tile_y;
+    double best = 1e300;
+    int bx = tx0, by = ty0;
+    int rc = PIXVOD_OK;
+    for (auto& c : cand) {
+        b->tile_x = c[0];
+        b->tile_y = c[1];
+        if ((rc = batch_build_work(b))) break;
+        BatchLaunch L = batch_launch_args(b);
+        // prologue and one warm-up pass (two buffer swaps), then the timed passes
+        if (launch_batch_passes(L, 1, true, false, b->stream) != hipSuccess) { rc = PIXVOD_EHIP; break; }
+        (void)hipEventRecord(b->ev0, b->stream);
+        if (launch_batch_passes(L, n_iters, false, false, b->stream) != hipSuccess) { rc = PIXVOD_EHIP; break; }
+        (void)hipEventRecord(b->ev1, b->stream);
+        if (hipStreamSynchronize(b->stream) != hipSuccess) { rc = PIXVOD_EHIP; break; }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, b->ev0, b->ev1);
+        if (ms < best) {
+            best = ms;
+            bx = c[0];
+            by = c[1];
+        }
+        for (int i = 0; i < b->n; ++i)
+            for (int k = 0; k < 2; ++k)
+                (void)hipMemcpyAsync(b->seq[i].X[k], snap[2 * i + k], (size_t)b->seq[i].plane * N_PLANES * sizeof(float),
+                                     hipMemcpyDeviceToDevice, b->stream);
+    }
+    (void)hipStreamSynchronize(b->stream);
+    for (float* p : snap)
+        if (p) (void)hipFree(p);
+    if (rc) return rc;
+    b->tile_x = bx;
+    b->tile_y = by;
+    rc = batch_build_work(b);
+    *tx_out = bx;
+    *ty_out = by;
+    return rc;
+}
+
+}  // extern "C"

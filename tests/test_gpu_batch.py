@@ -1,0 +1,145 @@
+"""Batched tracking (many sequences of mixed resolution per launch): the batch
+must reproduce per-sequence contexts bit for bit, for every tile shape, and
+its frame-step graph must replay consistently."""
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+PARAMS = dict(sigma_P=0.01, huber_k=10.0, init_inv_depth=0.5)
+
+
+def _seq_inputs(shapes, n_frames, seed=0):
+    """Small textured sequences: a keyframe and frames with sub-pixel motion."""
+    out = []
+    for k, (H, W) in enumerate(shapes):
+        rv = [0.001 * (k % 3), -0.002, 0.001]
+        tr = [0.004 + 0.001 * k, -0.002, 0.003]
+        frames = []
+        for f in range(n_frames):
+            s = (f + 1) / n_frames
+            p = synth.tiny_pair(seed + k, H=H, W=W, inv_depth=0.5 + 0.1 * (k % 4),
+                                rotvec=[x * s for x in rv], trans=[x * s for x in tr])
+            frames.append(p["I_t"])
+        out.append(dict(cam=p["cam"], I_s=p["I_s"], N_s=p["normals_s"], frames=frames))
+    return out
+
+
+def _K(cam):
+    return (cam.fx, cam.fy, cam.cx, cam.cy)
+
+
+def _make_batch(seqs, tile=None):
+    import paper_2606_03989_amd as pv
+    b = pv.Batch([(s["cam"].H, s["cam"].W) for s in seqs], [_K(s["cam"]) for s in seqs], **PARAMS)
+    if tile:
+        b.set_tile(*tile)
+    b.set_keyframes(list(range(len(seqs))), [s["I_s"] for s in seqs], [s["N_s"] for s in seqs])
+    return b
+
+
+SHAPES = [(24, 32), (29, 37), (48, 64), (7, 130)]
+
+
+def test_batch_equals_per_sequence_contexts():
+    import paper_2606_03989_amd as pv
+    seqs = _seq_inputs(SHAPES, 3)
+    b = _make_batch(seqs)
+    singles = []
+    for s in seqs:
+        t = pv.Tracker(s["cam"].H, s["cam"].W, _K(s["cam"]), **PARAMS)
+        t.set_keyframe(s["I_s"], s["N_s"])
+        singles.append(t)
+    for f in range(3):
+        rb = b.track([s["frames"][f] for s in seqs], 6, maps=True)
+        for i, (s, t) in enumerate(zip(seqs, singles)):
+            rs = t.track(s["frames"][f], 6)
+            np.testing.assert_array_equal(b.get_state(i), t.get_state())
+            # the pose mean is reduced per tile in the batch and per strided
+            # block in a single context: equal up to summation order
+            np.testing.assert_allclose(rb[i]["xi"], rs["xi"], rtol=1e-13, atol=1e-18)
+            np.testing.assert_array_equal(rb[i]["inv_depth"], rs["inv_depth"])
+            assert rb[i]["frames_since_keyframe"] == rs["frames_since_keyframe"] == f + 1
+            assert rb[i]["flags"] == rs["flags"]
+    print("batch == per-sequence contexts over 3 graph-replayed frame steps", flush=True)
+
+
+@pytest.mark.parametrize("tile", [(64, 4), (16, 16), (32, 1), (128, 2)])
+def test_tile_shape_does_not_change_results(tile):
+    seqs = _seq_inputs(SHAPES, 2)
+    ref = _make_batch(seqs, (64, 1))
+    b = _make_batch(seqs, tile)
+    for f in range(2):
+        ref.track([s["frames"][f] for s in seqs], 4)
+        b.track([s["frames"][f] for s in seqs], 4)
+    for i in range(len(seqs)):
+        np.testing.assert_array_equal(b.get_state(i), ref.get_state(i))
+
+
+def test_autotune_has_no_side_effects():
+    seqs = _seq_inputs(SHAPES, 2)
+    a = _make_batch(seqs)
+    b = _make_batch(seqs)
+    a.track([s["frames"][0] for s in seqs], 4)
+    b.track([s["frames"][0] for s in seqs], 4)
+    tx, ty = b.autotune(3)
+    assert tx * ty <= 256
+    print(f"autotuned tile {tx}x{ty}", flush=True)
+    for i in range(len(seqs)):
+        np.testing.assert_array_equal(a.get_state(i), b.get_state(i))
+    a.track([s["frames"][1] for s in seqs], 4)
+    b.track([s["frames"][1] for s in seqs], 4)
+    for i in range(len(seqs)):
+        np.testing.assert_array_equal(a.get_state(i), b.get_state(i))
+
+
+def test_batch_errors():
+    import paper_2606_03989_amd as pv
+    seqs = _seq_inputs(SHAPES[:2], 1)
+    b = pv.Batch([(s["cam"].H, s["cam"].W) for s in seqs], [_K(s["cam"]) for s in seqs], **PARAMS)
+    with pytest.raises(pv.PixvodError) as e:
+        b.track([s["frames"][0] for s in seqs], 3)
+    assert e.value.code == pv.ESTATE
+    with pytest.raises(pv.PixvodError) as e:
+        b.set_tile(32, 16)
+    assert e.value.code == pv.EINVAL
+    with pytest.raises(pv.PixvodError) as e:
+        pv.Batch([(2, 1)], [(10.0, 10.0, 1.0, 1.0)])
+    assert e.value.code == pv.EINVAL
+
+
+def test_full_size_mixed_batch_sampled_against_per_sequence():
+    # the 64-sequence mixed-resolution batch (128x96, 256x256, 320x240, 640x480)
+    # in the benchmark's launch configuration; sampled sequences are re-run
+    # alone and must match bit for bit
+    import paper_2606_03989_amd as pv
+    from synth.scenes import batch_resolution
+    rng = np.random.default_rng(5)
+    shapes = [batch_resolution(s) for s in range(64)]
+    Ks = [synth.Camera.default(H, W) for H, W in shapes]
+    imgs, frames, normals = [], [], []
+    for s, (H, W) in enumerate(shapes):
+        yy, xx = np.meshgrid(np.arange(H, dtype=np.float64), np.arange(W, dtype=np.float64), indexing="ij")
+        base = synth.value_noise_texture(xx / 4.0, yy / 4.0, 100 + s, 3, 0.5)
+        moved = synth.value_noise_texture((xx + 0.3) / 4.0, (yy - 0.2) / 4.0, 100 + s, 3, 0.5)
+        imgs.append(base.astype(np.float32))
+        frames.append(moved.astype(np.float32))
+        n = np.zeros((H, W, 3), np.float32)
+        n[..., 2] = -1.0
+        normals.append(n)
+    b = pv.Batch(shapes, [_K(k) for k in Ks], **PARAMS)
+    b.set_keyframes(list(range(64)), imgs, normals)
+    rb = b.track(frames, 3)
+    for s in (0, 1, 2, 3, 37, 63):
+        H, W = shapes[s]
+        t = pv.Tracker(H, W, _K(Ks[s]), **PARAMS)
+        t.set_keyframe(imgs[s], normals[s])
+        rs = t.track(frames[s], 3)
+        np.testing.assert_allclose(rb[s]["xi"], rs["xi"], rtol=1e-13, atol=1e-18)
+        np.testing.assert_array_equal(b.get_state(s), t.get_state())
+        t.close()
+    print(f"64-sequence batch frame step {b.last_step_ms():.2f} ms", flush=True)
+    b.close()

@@ -216,6 +216,62 @@ int pixvod_batch_last_step_ms(pixvod_batch* b, double* ms);
 /* Per-sequence state in the exchange layout of pixvod_get_state. */
 int pixvod_batch_get_state(pixvod_batch* b, int seq, void* dst, int where);
 
+/* ---------------------------------------------------------------------------
+ * Differentiation: unrolled tracking with a hand-written adjoint.
+ * A forward pass runs n_frames target frames of one keyframe with n_iters
+ * synchronous iterations each (per-factor semantics, fused kernels), starting
+ * every time from the state set by pixvod_unroll_set_keyframe: pose
+ * linearisation points at the identity, messages zero, log-depth
+ * -log(init_inv_depth). No re-anchoring happens inside the unroll. It records
+ * the canonical state every ckpt_every iterations (and at every frame start)
+ * on a device tape. The outputs per frame are the pose estimate xi (mean of
+ * the per-pixel pose tangents, Eq. estimator_avg) and the inverse-depth map.
+ * The backward pass walks the tape in reverse: for each checkpoint segment it
+ * recomputes the segment's states, then runs the reverse of every iteration
+ * (vector-Jacobian products of the marginals, the message step with its
+ * Schur complements, the update with its relinearisation and transport, and
+ * the photometric and prior factors), and returns the gradient of
+ *   sum_f xi_bar[f] . xi[f] + sum_f sum_i inv_depth_bar[f][i] inv_depth[f][i]
+ * with respect to the per-pixel photometric sigma map (Eq. distrb_photo), the
+ * normal-integration sigma (Eq. gbpni) and the Huber threshold. Any loss of
+ * the outputs is handled by passing its output cotangents. Stored FP32
+ * roundings are differentiated as the identity and discrete decisions (valid
+ * warp window, Huber branch, interpolation cell) as constants.
+ * The unroll always uses a sigma map; damping must be 0.
+ */
+typedef struct pixvod_unroll pixvod_unroll;
+
+/* H, W >= 2; 1 <= n_iters; 1 <= ckpt_every; 1 <= max_frames. Device memory
+ * holds max_frames * ceil(n_iters / ckpt_every) checkpoints of the state
+ * (123 * H * W floats each, rows padded to 64 floats) and ckpt_every states of
+ * one recomputed segment. */
+int pixvod_unroll_create(int H, int W, const pixvod_intrinsics* K, const pixvod_params* params, int max_frames,
+                         int n_iters, int ckpt_every, pixvod_unroll** out_unroll);
+int pixvod_unroll_destroy(pixvod_unroll* u);
+int pixvod_unroll_set_stream(pixvod_unroll* u, void* hip_stream);
+
+/* keyframe image (H*W) and normals (H*W*3), as pixvod_set_keyframe */
+int pixvod_unroll_set_keyframe(pixvod_unroll* u, const float* img, const float* normals, int where);
+
+/* frames: n_frames * H * W (1 <= n_frames <= max_frames), copied; sigma_map:
+ * H * W photometric sigmas (> 0); sigma_N > 0 and huber_k > 0 replace the
+ * creation parameters. xi_out (host, n_frames * 6 doubles) and inv_depth_out
+ * (n_frames * H * W floats at out_where) may be NULL. */
+int pixvod_unroll_forward(pixvod_unroll* u, const float* frames, int n_frames, int where, const float* sigma_map,
+                          int sigma_where, double sigma_N, double huber_k, double* xi_out, float* inv_depth_out,
+                          int out_where);
+
+/* Cotangents of the last forward's outputs: xi_bar (host, n_frames * 6) and
+ * inv_depth_bar (n_frames * H * W at `where`), either may be NULL (zero).
+ * Gradients: grad_sigma_map (H * W floats at grad_where, may be NULL),
+ * grad_sigma_N and grad_huber_k (host doubles, may be NULL). Needs a forward
+ * pass since the last keyframe; may be called several times per forward. */
+int pixvod_unroll_backward(pixvod_unroll* u, const double* xi_bar, const float* inv_depth_bar, int where,
+                           float* grad_sigma_map, int grad_where, double* grad_sigma_N, double* grad_huber_k);
+
+/* Durations (ms, HIP events on the stream) of the last forward and backward. */
+int pixvod_unroll_last_ms(const pixvod_unroll* u, double* forward_ms, double* backward_ms);
+
 /* Per-context message of the last failure; ctx == NULL gives the last
  * failure of a call that had no context (e.g. pixvod_create). */
 const char* pixvod_last_error(const pixvod_ctx* ctx);

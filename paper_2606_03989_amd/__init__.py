@@ -86,6 +86,16 @@ _SIGNATURES = {
     "pixvod_batch_autotune": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "pixvod_batch_last_step_ms": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "pixvod_batch_get_state": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int]),
+    "pixvod_unroll_create": (C.c_int, [C.c_int, C.c_int, C.POINTER(Intrinsics), C.POINTER(Params), C.c_int, C.c_int,
+                                       C.c_int, C.POINTER(C.c_void_p)]),
+    "pixvod_unroll_destroy": (C.c_int, [C.c_void_p]),
+    "pixvod_unroll_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "pixvod_unroll_set_keyframe": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "pixvod_unroll_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_double,
+                                        C.c_double, C.c_void_p, C.c_void_p, C.c_int]),
+    "pixvod_unroll_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int,
+                                         C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "pixvod_unroll_last_ms": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "pixvod_last_error": (C.c_char_p, [C.c_void_p]),
     "pixvod_version": (C.c_char_p, []),
 }
@@ -340,6 +350,125 @@ class Batch:
         s = np.empty((N_PLANES, H, W), np.float32)
         _batch_check(lib().pixvod_batch_get_state(self._h, int(seq), C.c_void_p(s.ctypes.data), HOST))
         return s
+
+
+class Unrolled:
+    """Differentiable unrolled tracking of target frames against one keyframe.
+
+    forward() runs n_iters GBP iterations per frame from the keyframe's
+    initial state and records a checkpoint every ckpt_every iterations on the
+    device; backward() runs the hand-written adjoint over that tape and returns
+    the gradients of <xi_bar, xi> + <inv_depth_bar, inv_depth> with respect to
+    the photometric sigma map, sigma_N and the Huber threshold. A context holds
+    the tape of its last forward only.
+    """
+
+    def __init__(self, H: int, W: int, K, n_iters: int, max_frames: int, ckpt_every: int = 10,
+                 params: Optional[Params] = None, **overrides):
+        self.H, self.W = int(H), int(W)
+        if params is None:
+            params = default_params(**overrides)
+        self.params = params
+        self.n_iters, self.max_frames = int(n_iters), int(max_frames)
+        Kc = Intrinsics(*[float(x) for x in K])
+        h = C.c_void_p()
+        _batch_check(lib().pixvod_unroll_create(self.H, self.W, C.byref(Kc), C.byref(params), self.max_frames,
+                                                self.n_iters, int(ckpt_every), C.byref(h)))
+        self._h = h
+        self.n_frames = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pixvod_unroll_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream=None):
+        s = None if stream is None else C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else stream)
+        _batch_check(lib().pixvod_unroll_set_stream(self._h, s))
+
+    def set_keyframe(self, img, normals):
+        pi, wi, ki = _ptr(img)
+        pn, wn, kn = _ptr(normals)
+        if wi != wn:
+            raise ValueError("image and normals must live in the same memory")
+        _batch_check(lib().pixvod_unroll_set_keyframe(self._h, C.c_void_p(pi), C.c_void_p(pn), wi))
+
+    def forward(self, frames, sigma_map, sigma_N: float, huber_k: float, out_device: bool = False):
+        """frames (F, H, W) float32; returns xi (F, 6) float64 numpy and the
+        inverse-depth maps (F, H, W) float32 (numpy, or a CUDA tensor)."""
+        pf, wf, kf = _ptr(frames)
+        ps, ws, ks = _ptr(sigma_map)
+        F = int(np.prod(frames.shape)) // (self.H * self.W)
+        xi = np.zeros((F, 6), np.float64)
+        if out_device:
+            rho = torch.empty((F, self.H, self.W), dtype=torch.float32, device="cuda")
+            pr, wr = rho.data_ptr(), DEVICE
+        else:
+            rho = np.empty((F, self.H, self.W), np.float32)
+            pr, wr = rho.ctypes.data, HOST
+        _batch_check(lib().pixvod_unroll_forward(self._h, C.c_void_p(pf), F, wf, C.c_void_p(ps), ws,
+                                                 float(sigma_N), float(huber_k), C.c_void_p(xi.ctypes.data),
+                                                 C.c_void_p(pr), wr))
+        self.n_frames = F
+        return xi, rho
+
+    def backward(self, xi_bar=None, inv_depth_bar=None, grad_device: bool = False):
+        """Gradients (sigma map (H, W) float32, sigma_N, huber_k) of the last
+        forward for the given output cotangents (None = zero)."""
+        xb = None
+        if xi_bar is not None:
+            xb = np.ascontiguousarray(np.asarray(xi_bar, dtype=np.float64).reshape(self.n_frames, 6))
+        pr, wr, kr = (None, HOST, None) if inv_depth_bar is None else _ptr(inv_depth_bar)
+        if grad_device:
+            g = torch.empty((self.H, self.W), dtype=torch.float32, device="cuda")
+            pg, wg = g.data_ptr(), DEVICE
+        else:
+            g = np.empty((self.H, self.W), np.float32)
+            pg, wg = g.ctypes.data, HOST
+        gN, gk = C.c_double(), C.c_double()
+        _batch_check(lib().pixvod_unroll_backward(self._h, None if xb is None else C.c_void_p(xb.ctypes.data),
+                                                  None if pr is None else C.c_void_p(pr), wr, C.c_void_p(pg), wg,
+                                                  C.byref(gN), C.byref(gk)))
+        return g, gN.value, gk.value
+
+    def last_ms(self):
+        """(forward ms, backward ms) of the last calls, timed with HIP events."""
+        f, b = C.c_double(), C.c_double()
+        _batch_check(lib().pixvod_unroll_last_ms(self._h, C.byref(f), C.byref(b)))
+        return f.value, b.value
+
+
+class _UnrolledTrack(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, unroll, frames, sigma_map, sigma_N, huber_k):
+        dev = sigma_map.device
+        xi, rho = unroll.forward(frames.detach().contiguous(), sigma_map.detach().to(torch.float32).contiguous(),
+                                 float(sigma_N), float(huber_k), out_device=dev.type == "cuda")
+        ctx.unroll = unroll
+        ctx.meta = (dev, sigma_map.dtype, sigma_N.dtype, huber_k.dtype)
+        rho_t = rho if isinstance(rho, torch.Tensor) else torch.from_numpy(rho)
+        return torch.from_numpy(xi).to(dev), rho_t
+
+    @staticmethod
+    def backward(ctx, xi_bar, rho_bar):
+        dev, sdt, ndt, kdt = ctx.meta
+        rb = rho_bar.detach().to(torch.float32).contiguous()
+        g, gN, gk = ctx.unroll.backward(xi_bar.detach().cpu().numpy(), rb, grad_device=rb.is_cuda)
+        g_t = (g if isinstance(g, torch.Tensor) else torch.from_numpy(g)).to(device=dev, dtype=sdt)
+        return (None, None, g_t, torch.tensor(gN, dtype=ndt, device=dev), torch.tensor(gk, dtype=kdt, device=dev))
+
+
+def unrolled_track(unroll: Unrolled, frames, sigma_map, sigma_N, huber_k):
+    """torch.autograd entry point: (xi (F, 6) float64, inverse depth (F, H, W))
+    as functions of the sigma map (H, W), sigma_N and huber_k (0-d tensors).
+    The backward pass is the library's adjoint; one graph per context at a time."""
+    return _UnrolledTrack.apply(unroll, frames, sigma_map, sigma_N, huber_k)
 
 
 def version() -> str:

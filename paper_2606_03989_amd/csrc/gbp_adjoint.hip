@@ -1,0 +1,467 @@
+// HIP kernels of the reverse sweep through unrolled GBP iterations (PixVOD,
+// arXiv 2606.03989) for gfx950: one lane per pixel, FP32 cotangent planes in
+// the state layout, FP64 algebra in registers.
+//
+// Reverse of one canonical iteration X -> X' (linearise + marginals, messages,
+// update + relinearise + transport; Sec. 3.4 and Sec. 4.1), given the
+// cotangent Xb' of X':
+//   forward recompute  marginals (29 planes) and new messages (116 planes) of X,
+//                      by the per-factor kernels;
+//   k_adj_update       reverse of the update at every pixel: cotangents of its
+//                      four new messages (Mb, 116 planes) and of its unary
+//                      information and point (Ub, 42 planes);
+//   k_adj_edges        every pixel, as the sender of its four outgoing
+//                      messages and the receiver of its four incoming ones:
+//                      cotangents of its marginals, of the residual's pose and
+//                      log-depth arguments, and of the stored messages the
+//                      sender subtracted (gathered from the neighbours' Mb, no
+//                      atomics);
+//   k_adj_belief       reverse of the marginals and of the unary factors:
+//                      completes Xb (cotangent of X) and accumulates the
+//                      per-pixel parameter gradients.
+#include "gbp_adjoint.h"
+#include "gbp_adjoint.hpp"
+
+namespace pv {
+
+constexpr int MSG_STRIDE = 29;   // per direction: eta 6, Lambda 21, normal eta, normal lambda
+constexpr int UB_TAU = 35;       // Ub: L_bar 28, eta_bar 7, tau_bar 6, ell_bar 1
+constexpr int UB_ELL = 41;
+constexpr int EB_P = 0;          // Eb: P_bar 21, p_bar 6, D_bar, dv_bar, eps_bar 6, ell_bar
+constexpr int EB_PV = 21;
+constexpr int EB_D = 27;
+constexpr int EB_DV = 28;
+constexpr int EB_EPS = 29;
+constexpr int EB_ELL = 35;
+
+__device__ inline bool pixel_2d(const Geo& g, int& u, int& v) {
+    u = blockIdx.x * blockDim.x + threadIdx.x;
+    v = blockIdx.y * blockDim.y + threadIdx.y;
+    return u < g.W && v < g.H;
+}
+
+// reverse of the update (k_pf_update): belief from the unary and the new
+// messages, mean m, relinearisation, transport of the messages
+__global__ __launch_bounds__(256) void k_adj_update(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
+                                                    const double* __restrict__ M, const float* __restrict__ Xb,
+                                                    double* __restrict__ Mb, double* __restrict__ Ub) {
+    int u, v;
+    if (!pixel_2d(g, u, v)) return;
+    const long p = pix_of(g, u, v);
+    const long pl = g.plane;
+    double tau[6], ell, R[9], t[3], L[28], eta[7];
+    load_point(X, g, p, tau, ell);
+    se3_exp(tau, R, t);
+    unary_factors(g, s, in, u, v, tau, R, t, ell, L, eta);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const double* md = M + (long)d * MSG_STRIDE * pl + p;
+#pragma unroll
+        for (int a = 0; a < 6; ++a) eta[a] += md[a * pl];
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+            for (int c = r; c < 6; ++c) L[s7(r, c)] += md[(6 + s6(r, c)) * pl];
+        eta[6] += md[27 * pl];
+        L[s7(6, 6)] += md[28 * pl];
+    }
+    double idg[7], m[7];
+    chol7(L, idg);
+#pragma unroll
+    for (int k = 0; k < 7; ++k) m[k] = eta[k];
+    chol7_solve(L, idg, m);
+    double Rm[9], tm[3], R1[9], t1[3], tn[6];
+    se3_exp(m, Rm, tm);
+    se3_compose(R, t, Rm, tm, R1, t1);
+    se3_log(R1, t1, tn);
+
+    // transport eta' = eta - Lambda m_p, ne' = ne - nl m6: contribution to m_bar
+    double mb[7] = {0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        int nu, nv;
+        if (!neighbour(g, u, v, d, nu, nv)) continue;
+        const double* md = M + (long)d * MSG_STRIDE * pl + p;
+        const float* xb = Xb + (long)(P_MID + d * MID_STRIDE) * pl + p;
+        double Lam[21], eb[6], y[6];
+#pragma unroll
+        for (int k = 0; k < 21; ++k) Lam[k] = md[(6 + k) * pl];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) eb[a] = (double)xb[a * pl];
+        sym_mv6(Lam, eb, y);
+#pragma unroll
+        for (int a = 0; a < 6; ++a) mb[a] -= y[a];
+        mb[6] -= md[28 * pl] * (double)Xb[(long)(P_MN + 2 * d) * pl + p];
+    }
+    // relinearisation tau' = Log(Exp(tau) Exp(m_p)):
+    //   d tau' = Jl(tau')^-1 Jl(tau) d tau + Jr(tau')^-1 Jr(m_p) d m_p
+    double tnb[6], a6[6], taub[6], b6[6], mpb[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) tnb[k] = (double)Xb[(long)(P_TAU + k) * pl + p];
+    const double ellnb = (double)Xb[(long)P_ELL * pl + p];
+    jac_invT_apply(tn, 1.0, tnb, a6);
+    jac_T_apply(tau, 1.0, a6, taub);
+    jac_invT_apply(tn, -1.0, tnb, b6);
+    jac_T_apply(m, -1.0, b6, mpb);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) mb[k] += mpb[k];
+    mb[6] += ellnb;
+    // m = B^-1 beta
+    double betab[7], Bb[28];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) betab[k] = mb[k];
+    chol7_solve(L, idg, betab);
+#pragma unroll
+    for (int k = 0; k < 28; ++k) Bb[k] = 0.0;
+    sym_outer_acc7(Bb, betab, m, -1.0);
+
+    // cotangents of the four new messages: transport + belief
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        double* o = Mb + (long)d * MSG_STRIDE * pl + p;
+        int nu, nv;
+        if (!neighbour(g, u, v, d, nu, nv)) {
+#pragma unroll
+            for (int k = 0; k < MSG_STRIDE; ++k) o[k * pl] = 0.0;
+            continue;
+        }
+        const float* xb = Xb + (long)(P_MID + d * MID_STRIDE) * pl + p;
+        double eb[6];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+            eb[a] = (double)xb[a * pl];
+            o[a * pl] = eb[a] + betab[a];
+        }
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+            for (int c = r; c < 6; ++c) {
+                const double tr = (r == c) ? eb[r] * m[r] : eb[r] * m[c] + eb[c] * m[r];
+                o[(6 + s6(r, c)) * pl] = (double)xb[(6 + s6(r, c)) * pl] - tr + Bb[s7(r, c)];
+            }
+        const double neb = (double)Xb[(long)(P_MN + 2 * d) * pl + p];
+        const double nlb = (double)Xb[(long)(P_MN + 2 * d + 1) * pl + p];
+        o[27 * pl] = neb + betab[6];
+        o[28 * pl] = nlb - neb * m[6] + Bb[s7(6, 6)];
+    }
+    double* ub = Ub + p;
+#pragma unroll
+    for (int k = 0; k < 28; ++k) ub[k * pl] = Bb[k];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) ub[(28 + k) * pl] = betab[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) ub[(UB_TAU + k) * pl] = taub[k];
+    ub[UB_ELL * pl] = ellnb;
+}
+
+// reverse of the message step (k_pf_messages) at every pixel j, as receiver
+// (residual of its incoming messages) and as sender (its marginals and the
+// stored messages it subtracted). Writes the sender part of j's message-slot
+// cotangents to Xbo and the marginal / perturbation cotangents to Eb.
+__global__ __launch_bounds__(256) void k_adj_edges(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
+                                                   const double* __restrict__ marg, const double* __restrict__ M,
+                                                   const double* __restrict__ Mb, float* __restrict__ Xbo,
+                                                   double* __restrict__ Eb, double* __restrict__ gN) {
+    int u, v;
+    if (!pixel_2d(g, u, v)) return;
+    const long pj = pix_of(g, u, v);
+    const long pl = g.plane;
+    double tau[6], ell, R[9], t[3];
+    load_point(X, g, pj, tau, ell);
+    se3_exp(tau, R, t);
+    double Pb[21], pb[6], epsb[6];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) Pb[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) pb[k] = epsb[k] = 0.0;
+    double Db = 0.0, dvb = 0.0, ellb = 0.0, lamNb = 0.0;
+    for (int d = 0; d < 4; ++d) {
+        float* xo = Xbo + (long)(P_MID + d * MID_STRIDE) * pl + pj;
+        float* xn = Xbo + (long)(P_MN + 2 * d) * pl + pj;
+        int nu, nv;
+        if (!neighbour(g, u, v, d, nu, nv)) {
+            for (int k = 0; k < MID_STRIDE; ++k) xo[k * pl] = 0.0f;
+            xn[0] = xn[pl] = 0.0f;
+            continue;
+        }
+        const long pi = pix_of(g, nu, nv);
+        const int o = opposite(d);
+        const double* Mj = M + (long)d * MSG_STRIDE * pl + pj;
+        const double* Mbj = Mb + (long)d * MSG_STRIDE * pl + pj;
+        const double* Mi = M + (long)o * MSG_STRIDE * pl + pi;
+        const double* Mbi = Mb + (long)o * MSG_STRIDE * pl + pi;
+        // residual of the message into j from i, r = Log(Exp(tau_i)^-1 Exp(tau_j));
+        // the message into i from j uses -r
+        double ti[6], elli, Ri[9], tri[3], r[6];
+        load_point(X, g, pi, ti, elli);
+        se3_exp(ti, Ri, tri);
+        se3_between(Ri, tri, R, t, r);
+        // eta_new = h - Lp r on both sides: receiver r_bar = -Lp_j eb_j, sender
+        // r_bar = -Lp_i eb_i with d(-r)/d(eps_j) = -Jr(r)^-1 ... combined:
+        //   eps_j += Jr(r)^-T (Lp_i eb_i - Lp_j eb_j)
+        double rb[6];
+        {
+            double Lam[21], e[6], y1[6], y2[6];
+#pragma unroll
+            for (int k = 0; k < 21; ++k) Lam[k] = Mj[(6 + k) * pl];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) e[a] = Mbj[a * pl];
+            sym_mv6(Lam, e, y1);
+#pragma unroll
+            for (int k = 0; k < 21; ++k) Lam[k] = Mi[(6 + k) * pl];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) e[a] = Mbi[a * pl];
+            sym_mv6(Lam, e, y2);
+#pragma unroll
+            for (int a = 0; a < 6; ++a) rb[a] = y2[a] - y1[a];
+        }
+        double e6[6];
+        jac_invT_apply(r, -1.0, rb, e6);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) epsb[k] += e6[k];
+
+        // sender: the partial of the message into i from j's variable-to-factor
+        // message (j's marginal minus j's stored message from this factor)
+        double V[21], vv[6], Lpb[21], hb[6], Vb[21], vb[6];
+#pragma unroll
+        for (int k = 0; k < 21; ++k) {
+            V[k] = marg[(long)k * pl + pj] - (double)X[(long)(P_MID + d * MID_STRIDE + 6 + k) * pl + pj];
+            Lpb[k] = Mbi[(6 + k) * pl];
+        }
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+            vv[a] = marg[(long)(21 + a) * pl + pj] - (double)X[(long)(P_MID + d * MID_STRIDE + a) * pl + pj];
+            hb[a] = Mbi[a * pl];
+        }
+        // eta_i = h - Lp (-r): Lp_bar += sym(hb r^T)
+        sym_outer_acc6(Lpb, hb, r, 1.0);
+        identity_partial_adjoint(s.lamR, V, vv, Lpb, hb, Vb, vb);
+#pragma unroll
+        for (int k = 0; k < 21; ++k) {
+            Pb[k] += Vb[k];
+            xo[(6 + k) * pl] = (float)(-Vb[k]);
+        }
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+            pb[a] += vb[a];
+            xo[a * pl] = (float)(-vb[a]);
+        }
+
+        // normal-integration factor of the edge
+        double nsb = 0.0, nlsb = 0.0;
+        double rn_j, rn_i;
+        if (s.lamN > 0.0 && normal_residual(g, in, pj, pi, d, ell, elli, rn_j)) {
+            normal_residual(g, in, pi, pj, o, elli, ell, rn_i);
+            // ne_new = h - lp rn: receiver j and sender j (rn_i depends on ell_j with -1)
+            ellb += -Mj[28 * pl] * Mbj[27 * pl] + Mi[28 * pl] * Mbi[27 * pl];
+            const double neb = Mbi[27 * pl], nlb = Mbi[28 * pl];
+            const double ls = marg[27L * pl + pj] - (double)X[(long)(P_MN + 2 * d + 1) * pl + pj];
+            const double vs = marg[28L * pl + pj] - (double)X[(long)(P_MN + 2 * d) * pl + pj];
+            double lsb, vsb, lnb;
+            normal_partial_adjoint(s.lamN, ls, vs, nlb - neb * rn_i, neb, lsb, vsb, lnb);
+            Db += lsb;
+            dvb += vsb;
+            lamNb += lnb;
+            nsb = -vsb;
+            nlsb = -lsb;
+        }
+        xn[0] = (float)nsb;
+        xn[pl] = (float)nlsb;
+    }
+    double* eb = Eb + pj;
+#pragma unroll
+    for (int k = 0; k < 21; ++k) eb[(EB_P + k) * pl] = Pb[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        eb[(EB_PV + k) * pl] = pb[k];
+        eb[(EB_EPS + k) * pl] = epsb[k];
+    }
+    eb[EB_D * pl] = Db;
+    eb[EB_DV * pl] = dvb;
+    eb[EB_ELL * pl] = ellb;
+    gN[pj] += lamNb;
+}
+
+// reverse of the marginals and of the unary factors; completes Xbo
+__global__ __launch_bounds__(256) void k_adj_belief(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
+                                                    const double* __restrict__ Ub, const double* __restrict__ Eb,
+                                                    float* __restrict__ Xbo, double* __restrict__ gsig,
+                                                    double* __restrict__ gk) {
+    int u, v;
+    if (!pixel_2d(g, u, v)) return;
+    const long p = pix_of(g, u, v);
+    const long pl = g.plane;
+    double tau[6], ell, R[9], t[3], L[28], eta[7];
+    load_point(X, g, p, tau, ell);
+    se3_exp(tau, R, t);
+    unary_factors(g, s, in, u, v, tau, R, t, ell, L, eta);
+    {
+        float mid[4][27], mn[4][2];
+        load_messages(X, g, p, mid, mn);
+        add_messages(L, eta, mid, mn);
+    }
+    const double* eb = Eb + p;
+    double Pb[21], pb[6];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) Pb[k] = eb[(EB_P + k) * pl];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) pb[k] = eb[(EB_PV + k) * pl];
+    double BbS[28], ebS[7];
+#pragma unroll
+    for (int k = 0; k < 28; ++k) BbS[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) ebS[k] = 0.0;
+    marginals_adjoint(L, eta, Pb, pb, eb[EB_D * pl], eb[EB_DV * pl], BbS, ebS);
+
+    const double* ub = Ub + p;
+    double Lb[28], etab[7], epsb[6], taub[6];
+#pragma unroll
+    for (int k = 0; k < 28; ++k) Lb[k] = ub[k * pl] + BbS[k];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) etab[k] = ub[(28 + k) * pl] + ebS[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        epsb[k] = eb[(EB_EPS + k) * pl];
+        taub[k] = ub[(UB_TAU + k) * pl];
+    }
+    double ellb = ub[UB_ELL * pl] + eb[EB_ELL * pl];
+    double sigb = 0.0, kb = 0.0;
+    unary_adjoint(g, s, in, u, v, tau, R, t, ell, Lb, etab, epsb, taub, ellb, sigb, kb);
+    double te[6];
+    jac_T_apply(tau, -1.0, epsb, te);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Xbo[(long)(P_TAU + k) * pl + p] = (float)(taub[k] + te[k]);
+    Xbo[(long)P_ELL * pl + p] = (float)ellb;
+    // every stored message enters the belief
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        int nu, nv;
+        if (!neighbour(g, u, v, d, nu, nv)) continue;
+        float* xo = Xbo + (long)(P_MID + d * MID_STRIDE) * pl + p;
+#pragma unroll
+        for (int a = 0; a < 6; ++a) xo[a * pl] = (float)((double)xo[a * pl] + ebS[a]);
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+            for (int c = r; c < 6; ++c)
+                xo[(6 + s6(r, c)) * pl] = (float)((double)xo[(6 + s6(r, c)) * pl] + BbS[s7(r, c)]);
+        float* xn = Xbo + (long)(P_MN + 2 * d) * pl + p;
+        xn[0] = (float)((double)xn[0] + ebS[6]);
+        xn[pl] = (float)((double)xn[pl] + BbS[s7(6, 6)]);
+    }
+    gsig[p] += sigb;
+    gk[p] += kb;
+}
+
+// cotangents of the per-frame outputs: pose mean (Eq. estimator_avg) and the
+// inverse-depth map rho = exp(-ell)
+__global__ void k_adj_inject(Geo g, const float* __restrict__ Xend, float* __restrict__ Xb, PoseBar xb,
+                             const float* __restrict__ rhob) {
+    int u, v;
+    if (!pixel_2d(g, u, v)) return;
+    const long p = pix_of(g, u, v);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        float* q = Xb + (long)(P_TAU + k) * g.plane + p;
+        *q = (float)((double)*q + xb.v[k]);
+    }
+    if (rhob) {
+        const double rho = exp(-(double)Xend[(long)P_ELL * g.plane + p]);
+        float* q = Xb + (long)P_ELL * g.plane + p;
+        *q = (float)((double)*q - rho * (double)rhob[(long)v * g.W + u]);
+    }
+}
+
+// per block: sums of two FP64 planes (deterministic two-stage reduction)
+constexpr int SUM_THREADS = 256;
+
+__global__ __launch_bounds__(SUM_THREADS) void k_sum2(Geo g, const double* __restrict__ a,
+                                                      const double* __restrict__ b, double* __restrict__ partial) {
+    __shared__ double sh[2][SUM_THREADS];
+    double s0 = 0.0, s1 = 0.0;
+    const long N = (long)g.H * g.W;
+    for (long i = (long)blockIdx.x * SUM_THREADS + threadIdx.x; i < N; i += (long)gridDim.x * SUM_THREADS) {
+        const long p = pix_of(g, (int)(i % g.W), (int)(i / g.W));
+        s0 += a[p];
+        s1 += b[p];
+    }
+    sh[0][threadIdx.x] = s0;
+    sh[1][threadIdx.x] = s1;
+    __syncthreads();
+    for (int w = SUM_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 2) partial[(long)blockIdx.x * 2 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void k_sum2_final(int nblocks, const double* __restrict__ partial, double* __restrict__ result) {
+    const int k = threadIdx.x;
+    if (k >= 2) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += partial[(long)b * 2 + k];
+    result[k] = s;
+}
+
+// FP64 plane -> dense FP32 map
+__global__ void k_plane_to_dense(Geo g, const double* __restrict__ src, float* __restrict__ dst) {
+    int u, v;
+    if (!pixel_2d(g, u, v)) return;
+    dst[(long)v * g.W + u] = (float)src[pix_of(g, u, v)];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+static const dim3 kAdjBlock(64, 4);
+static dim3 adj_grid(const Geo& g) { return dim3((g.W + 63) / 64, (g.H + 3) / 4); }
+
+hipError_t launch_adj_update(const Geo& g, const Strengths& s, const Inputs& in, const float* X, const double* M,
+                             const float* Xb, double* Mb, double* Ub, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_update, adj_grid(g), kAdjBlock, 0, st, g, s, in, X, M, Xb, Mb, Ub);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_edges(const Geo& g, const Strengths& s, const Inputs& in, const float* X, const double* marg,
+                            const double* M, const double* Mb, float* Xbo, double* Eb, double* gN, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_edges, adj_grid(g), kAdjBlock, 0, st, g, s, in, X, marg, M, Mb, Xbo, Eb, gN);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_belief(const Geo& g, const Strengths& s, const Inputs& in, const float* X, const double* Ub,
+                             const double* Eb, float* Xbo, double* gsig, double* gk, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_belief, adj_grid(g), kAdjBlock, 0, st, g, s, in, X, Ub, Eb, Xbo, gsig, gk);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_inject(const Geo& g, const float* Xend, float* Xb, const PoseBar& xb, const float* rhob,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_inject, adj_grid(g), kAdjBlock, 0, st, g, Xend, Xb, xb, rhob);
+    return hipGetLastError();
+}
+
+int sum2_blocks(const Geo& g) {
+    const long N = (long)g.H * g.W;
+    long b = (N + SUM_THREADS * 8 - 1) / (SUM_THREADS * 8);
+    if (b < 1) b = 1;
+    if (b > 1024) b = 1024;
+    return (int)b;
+}
+
+hipError_t launch_sum2(const Geo& g, const double* a, const double* b, double* partial, double* result,
+                       hipStream_t st) {
+    const int nb = sum2_blocks(g);
+    hipLaunchKernelGGL(k_sum2, dim3(nb), dim3(SUM_THREADS), 0, st, g, a, b, partial);
+    hipLaunchKernelGGL(k_sum2_final, dim3(1), dim3(64), 0, st, nb, partial, result);
+    return hipGetLastError();
+}
+
+hipError_t launch_plane_to_dense(const Geo& g, const double* src, float* dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_plane_to_dense, adj_grid(g), kAdjBlock, 0, st, g, src, dst);
+    return hipGetLastError();
+}
+
+}  // namespace pv

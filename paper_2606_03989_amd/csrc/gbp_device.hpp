@@ -571,6 +571,74 @@ __device__ inline bool depth_marginal(const double L[28], const double eta[7], d
 }
 
 // ---------------------------------------------------------------------------
+// grid access
+
+__device__ inline long pix_of(const Geo& g, int u, int v) { return (long)v * g.pitch + u; }
+
+__device__ inline bool neighbour(const Geo& g, int u, int v, int d, int& nu, int& nv) {
+    nu = u + (d == DIR_L ? -1 : (d == DIR_R ? 1 : 0));
+    nv = v + (d == DIR_U ? -1 : (d == DIR_D ? 1 : 0));
+    return nu >= 0 && nu < g.W && nv >= 0 && nv < g.H;
+}
+
+__device__ inline void load_point(const float* __restrict__ X, const Geo& g, long p, double tau[6], double& ell) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) tau[k] = (double)X[(P_TAU + k) * g.plane + p];
+    ell = (double)X[P_ELL * g.plane + p];
+}
+
+// normal-integration target and the residual seen by a receiver at pixel i
+// whose neighbour j lies in direction d; false if the edge is inactive.
+// Eq. (gbpni): r = (ell_b - ell_a) + c_a with a the left/upper pixel.
+__device__ inline bool normal_residual(const Geo& g, const Inputs& in, long pi, long pj, int d,
+                                       double ell_i, double ell_j, double& r_recv) {
+    float c;
+    double sgn;
+    if (d == DIR_L) { c = in.cxt[pj]; sgn = 1.0; }         // a = j, b = i
+    else if (d == DIR_R) { c = in.cxt[pi]; sgn = -1.0; }   // a = i, b = j
+    else if (d == DIR_U) { c = in.cyt[pj]; sgn = 1.0; }
+    else { c = in.cyt[pi]; sgn = -1.0; }
+    if (!isfinite(c)) return false;
+    // receiver's Jacobian is +1 when it is b: r_recv = (ell_b - ell_a + c) * (+1 if b)
+    r_recv = (sgn > 0.0) ? (ell_i - ell_j + (double)c) : (ell_i - ell_j - (double)c);
+    return true;
+}
+
+__device__ inline bool normal_active(const Geo& g, const Inputs& in, long pi, long pj, int d) {
+    float c = (d == DIR_L) ? in.cxt[pj] : (d == DIR_R) ? in.cxt[pi] : (d == DIR_U) ? in.cyt[pj] : in.cyt[pi];
+    return isfinite(c);
+}
+
+__device__ inline void load_messages(const float* __restrict__ X, const Geo& g, long p, float mid[4][27],
+                                     float mn[4][2]) {
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+#pragma unroll
+        for (int k = 0; k < 27; ++k) mid[d][k] = X[(long)(P_MID + d * MID_STRIDE + k) * g.plane + p];
+        mn[d][0] = X[(long)(P_MN + 2 * d) * g.plane + p];
+        mn[d][1] = X[(long)(P_MN + 2 * d + 1) * g.plane + p];
+    }
+}
+
+// B += messages (embedded: identity -> pose block, normal -> depth entry)
+__device__ inline void add_messages(double L[28], double eta[7], const float mid[4][27], const float mn[4][2]) {
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+#pragma unroll
+        for (int a = 0; a < 6; ++a) eta[a] += (double)mid[d][a];
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+            for (int c = r; c < 6; ++c) L[s7(r, c)] += (double)mid[d][6 + s6(r, c)];
+    }
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        eta[6] += (double)mn[d][0];
+        L[s7(6, 6)] += (double)mn[d][1];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // factor-to-variable messages, split into the part the sender computes from
 // its variable-to-factor message (the "partial", independent of the
 // receiver's linearisation point) and the receiver's completion with the

@@ -18,6 +18,10 @@ hipError_t launch_keyframe_prep(const Geo& g, const float* img, const float* nor
 hipError_t launch_init_state(const Geo& g, float* X, float ell0, hipStream_t st);
 hipError_t launch_pf_iteration(const Geo& g, const Strengths& s, const Inputs& in, float* X, double* marg,
                                double* M, float* var_ll, float* valid, float beta, int* health, hipStream_t st);
+// the first two steps of a per-factor iteration (marginals, then the new
+// messages) without the update: X is left unchanged
+hipError_t launch_pf_marginals_messages(const Geo& g, const Strengths& s, const Inputs& in, const float* X,
+                                        double* marg, double* M, float* valid, int* health, hipStream_t st);
 hipError_t launch_fu_prologue(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* Y,
                               int* health, hipStream_t st);
 hipError_t launch_fu_iterate(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* Y,

@@ -15,6 +15,7 @@
 #include "../../include/pixvod.h"
 #include "gbp_device.hpp"
 #include "gbp_kernels.h"
+#include "runtime_internal.h"
 
 using namespace pv;
 
@@ -138,34 +139,6 @@ static double inv_sq(float s) {
     return 1.0 / ((double)s * (double)s);
 }
 
-static Strengths strengths_of(const pixvod_ctx* c) {
-    Strengths s;
-    std::memset(&s, 0, sizeof(s));
-    s.lamP = inv_sq(c->P.sigma_P);
-    s.lamR = inv_sq(c->P.sigma_R);
-    s.lamN = inv_sq(c->P.sigma_N);
-    s.lamD = inv_sq(c->P.sigma_D);
-    s.inv_sigD = 1.0 / (double)c->P.sigma_D;
-    s.huber_k = c->P.huber_k;
-    s.prior_ell = c->P.prior_log_depth;
-    bool ident = true;
-    double xi[6];
-    for (int k = 0; k < 6; ++k) {
-        xi[k] = c->P.prior_xi[k];
-        ident = ident && (xi[k] == 0.0);
-    }
-    double T[16], Ti[16];
-    host_se3_exp(xi, T);
-    host_se3_inverse(T, Ti);
-    for (int r = 0; r < 3; ++r) {
-        for (int cc = 0; cc < 3; ++cc) s.prior_R[r * 3 + cc] = Ti[r * 4 + cc];
-        s.prior_t[r] = Ti[r * 4 + 3];
-    }
-    s.prior_is_identity = ident ? 1 : 0;
-    s.has_sigma_map = c->has_sigma ? 1 : 0;
-    return s;
-}
-
 static Inputs inputs_of(const pixvod_ctx* c) {
     Inputs in;
     in.Is = c->Is;
@@ -188,6 +161,40 @@ static bool finite_params(const pixvod_params* p) {
     return p->sigma_D > 0 && p->sigma_P > 0 && p->sigma_R > 0 && p->sigma_N > 0 && p->huber_k > 0 &&
            p->init_inv_depth > 0 && p->damping >= 0 && p->damping < 1 && p->kf_max_frames >= 1;
 }
+
+Strengths pv::strengths_from(const pixvod_params& P, bool has_sigma_map) {
+    Strengths s;
+    std::memset(&s, 0, sizeof(s));
+    s.lamP = inv_sq(P.sigma_P);
+    s.lamR = inv_sq(P.sigma_R);
+    s.lamN = inv_sq(P.sigma_N);
+    s.lamD = inv_sq(P.sigma_D);
+    s.inv_sigD = 1.0 / (double)P.sigma_D;
+    s.huber_k = P.huber_k;
+    s.prior_ell = P.prior_log_depth;
+    bool ident = true;
+    double xi[6];
+    for (int k = 0; k < 6; ++k) {
+        xi[k] = P.prior_xi[k];
+        ident = ident && (xi[k] == 0.0);
+    }
+    double T[16], Ti[16];
+    host_se3_exp(xi, T);
+    host_se3_inverse(T, Ti);
+    for (int r = 0; r < 3; ++r) {
+        for (int cc = 0; cc < 3; ++cc) s.prior_R[r * 3 + cc] = Ti[r * 4 + cc];
+        s.prior_t[r] = Ti[r * 4 + 3];
+    }
+    s.prior_is_identity = ident ? 1 : 0;
+    s.has_sigma_map = has_sigma_map ? 1 : 0;
+    return s;
+}
+
+static Strengths strengths_of(const pixvod_ctx* c) { return strengths_from(c->P, c->has_sigma); }
+
+void pv::record_error(const std::string& msg) { g_last_error = msg; }
+
+bool pv::params_valid(const pixvod_params* p) { return finite_params(p); }
 
 template <typename T>
 static int dev_alloc(pixvod_ctx* c, T** p, size_t n) {

@@ -95,3 +95,47 @@ def make_tracker(w, schedule=0):
     t.set_schedule(schedule)
     t.set_keyframe(w["I_s"], w["N_s"])
     return t
+
+
+def diff_crop_workload(size: int = 24, n_frames: int = 2, seed: int = 3):
+    """Centred size x size crop of the 320x240 differentiation sequence
+    (intrinsics shifted by the crop origin), a perturbed sigma_D map around
+    the sequence's 5e-3 and random output cotangents."""
+    w = sequence_workload("diff320", n_frames)
+    cam = w["cam"]
+    x0, y0 = (cam.W - size) // 2, (cam.H - size) // 2
+    crop = lambda a: np.ascontiguousarray(a[y0:y0 + size, x0:x0 + size])
+    ccam = synth.Camera(H=size, W=size, fx=cam.fx, fy=cam.fy, cx=cam.cx - x0, cy=cam.cy - y0)
+    rng = np.random.default_rng(seed)
+    sig = (5e-3 * (1.0 + 0.2 * rng.uniform(-1.0, 1.0, (size, size)))).astype(np.float32)
+    cxi = rng.normal(size=(n_frames, 6))
+    crho = (rng.normal(size=(n_frames, size, size)) / (size * size)).astype(np.float32)
+    return dict(cam=ccam, I_s=crop(w["I_s"]), N_s=crop(w["N_s"]), frames=[crop(f) for f in w["frames"]],
+                sigma_map=sig, sigma_N=float(np.float32(1e-3)), huber_k=10.0, kw=dict(sigma_P=0.01), cxi=cxi, crho=crho)
+
+
+def diff_full_workload(n_frames: int = 1, seed: int = 4):
+    """The full 320x240 differentiation sequence with a perturbed sigma map."""
+    w = sequence_workload("diff320", n_frames)
+    cam = w["cam"]
+    rng = np.random.default_rng(seed)
+    sig = (5e-3 * (1.0 + 0.2 * rng.uniform(-1.0, 1.0, (cam.H, cam.W)))).astype(np.float32)
+    cxi = rng.normal(size=(n_frames, 6))
+    crho = (rng.normal(size=(n_frames, cam.H, cam.W)) / (cam.H * cam.W)).astype(np.float32)
+    return dict(cam=cam, I_s=w["I_s"], N_s=w["N_s"], frames=w["frames"], sigma_map=sig, sigma_N=float(np.float32(1e-3)),
+                huber_k=10.0, kw=dict(sigma_P=0.01), cxi=cxi, crho=crho)
+
+
+def make_unroll(w, n_iters: int, ckpt_every: int):
+    import paper_2606_03989_amd as pv
+    cam = w["cam"]
+    u = pv.Unrolled(cam.H, cam.W, K_of(cam), n_iters=n_iters, max_frames=len(w["frames"]),
+                    ckpt_every=ckpt_every, **w["kw"])
+    u.set_keyframe(w["I_s"], w["N_s"])
+    return u
+
+
+def make_unrolled_oracle(w, n_iters: int):
+    from oracle.gradient import UnrolledOracle
+    return UnrolledOracle(w["cam"], w["I_s"], w["N_s"], w["frames"], n_iters, w["sigma_map"], w["sigma_N"],
+                          w["huber_k"], **w["kw"])

@@ -244,6 +244,81 @@ def run_batch(n_seq: int, steps: int, iters: int, plain_steps: int):
                 resolutions="128x96, 256x256, 320x240, 640x480 (16 each)")
 
 
+DIFF_PARAMS = dict(sigma_P=0.01, huber_k=10.0)
+
+
+def run_adjoint(n_frames: int, iters: int, ckpt: int, reps: int):
+    """Forward + adjoint over the 320x240 differentiation sequence: n_frames
+    frames of `iters` unrolled iterations with a checkpoint every `ckpt`, the
+    adjoint for output cotangents of the pose and inverse-depth outputs
+    (random, seeded), against the plain fused forward on the same frames."""
+    import numpy as np
+    import torch
+    import paper_2606_03989_amd as pv
+    from synth.scenes import SEQUENCE_CONFIGS, make_sequence_scene, render_sequence_frame, sequence_poses
+    cfg = SEQUENCE_CONFIGS["diff320"]
+    scene, cam = make_sequence_scene(cfg)
+    poses = sequence_poses(cfg)
+    I0, _, N0, _ = render_sequence_frame(cfg, scene, cam, poses, 0, keyframe=True)
+    frames = np.stack([render_sequence_frame(cfg, scene, cam, poses, f)[0] for f in range(1, n_frames + 1)])
+    H, W = cam.H, cam.W
+    K = (cam.fx, cam.fy, cam.cx, cam.cy)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    d_fr = torch.from_numpy(frames.astype(np.float32)).to(dev)
+    d_I0, d_N0 = torch.from_numpy(I0).to(dev), torch.from_numpy(np.ascontiguousarray(N0)).to(dev)
+    sig = torch.full((H, W), 5e-3, dtype=torch.float32, device=dev)
+    rng = np.random.default_rng(11)
+    cxi = rng.normal(size=(n_frames, 6))
+    crho = torch.from_numpy((rng.normal(size=(n_frames, H, W)) / (H * W)).astype(np.float32)).to(dev)
+    u = pv.Unrolled(H, W, K, n_iters=iters, max_frames=n_frames, ckpt_every=ckpt, **DIFF_PARAMS)
+    u.set_stream(stream)
+    u.set_keyframe(d_I0, d_N0)
+    u.forward(d_fr, sig, 1e-3, DIFF_PARAMS["huber_k"], out_device=True)      # warm-up
+    u.backward(cxi, crho, grad_device=True)
+    torch.cuda.synchronize()
+    tf = tb = 0.0
+    for _ in range(reps):
+        a = time.perf_counter()
+        u.forward(d_fr, sig, 1e-3, DIFF_PARAMS["huber_k"], out_device=True)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        u.backward(cxi, crho, grad_device=True)
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        tf += b - a
+        tb += c - b
+    fwd_ms, bwd_ms = u.last_ms()
+    u.close()
+    t = pv.Tracker(H, W, K, sigma_N=1e-3, **DIFF_PARAMS)
+    t.set_stream(stream)
+    t.set_sigma_map(sig)
+    t.set_keyframe(d_I0, d_N0)
+    for f in range(n_frames):
+        t.track(d_fr[f], iters, maps=False)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(reps):
+        t.set_keyframe(d_I0, d_N0)
+        for f in range(n_frames):
+            t.track(d_fr[f], iters, maps=False)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - a
+    t.close()
+    work = H * W * iters * n_frames * reps / 1e6
+    v_fa = work / (tf + tb)
+    v_plain = work / tp
+    log(f"forward+adjoint: 320x240, {n_frames} frames x {iters} iterations, checkpoint every {ckpt}: "
+        f"forward {tf * 1e3 / reps:.1f} ms, adjoint {tb * 1e3 / reps:.1f} ms -> {v_fa:.1f} Mpx-iter/s; "
+        f"plain forward {tp * 1e3 / reps:.1f} ms -> {v_plain:.1f} Mpx-iter/s")
+    return dict(value=round(v_fa, 2), unit="Mpixel-iter/s (forward px-iter / (forward with tape + adjoint))",
+                workload=f"diff320 320x240, {n_frames} frames x {iters} unrolled iterations, checkpoint every {ckpt}",
+                forward_ms=round(tf * 1e3 / reps, 3), adjoint_ms=round(tb * 1e3 / reps, 3),
+                forward_event_ms=round(fwd_ms, 3), adjoint_event_ms=round(bwd_ms, 3),
+                plain_forward_value=round(v_plain, 1), plain_forward_ms=round(tp * 1e3 / reps, 3),
+                ratio_vs_plain=round(v_fa / v_plain, 4), gradients="sigma_D map, sigma_N, huber_k")
+
+
 def cpu_baseline(iters: int):
     """The FP64 oracle on the first frame of the same workload, `iters` iterations."""
     import oracle
@@ -302,6 +377,8 @@ def main():
     ap.add_argument("--probe", action="store_true", help="short run for hardware counters; no JSON line")
     ap.add_argument("--batch-steps", type=int, default=4, help="timed frame steps of the 64-sequence batch (0: skip)")
     ap.add_argument("--batch-seqs", type=int, default=64)
+    ap.add_argument("--adjoint-frames", type=int, default=29,
+                    help="target frames of the forward+adjoint leg (the 30-frame sequence after its keyframe; 0: skip)")
     args = ap.parse_args()
     if args.probe:
         probe()
@@ -315,6 +392,7 @@ def main():
 
     g = run_gpu(args)
     batched = run_batch(args.batch_seqs, args.batch_steps, 15, max(1, args.batch_steps // 2)) if args.batch_steps > 0 else None
+    adjoint = run_adjoint(args.adjoint_frames, 30, 10, 2) if args.adjoint_frames > 0 else None
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_iters)
     out = {
         "metric": "GBP Mpixel-iter/s at 640x480 + % HBM roofline; batched & fwd+adjoint vs plain",
@@ -336,6 +414,7 @@ def main():
         "cpu_baseline": cpu,
         "per_factor": g["per_factor"],
         "batched": batched,
+        "forward_adjoint": adjoint,
     }
     print(json.dumps(out), flush=True)
 

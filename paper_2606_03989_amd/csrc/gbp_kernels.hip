@@ -705,7 +705,7 @@ hipError_t launch_batch_passes(const BatchLaunch& b, int n_iters, bool prologue,
 // launchers
 
 static dim3 grid2d(const Geo& g, dim3 b) { return dim3((g.W + b.x - 1) / b.x, (g.H + b.y - 1) / b.y); }
-static const dim3 kBlock(64, 4);
+static const dim3 kBlock(64, 1);
 
 hipError_t launch_frame_prep(const Geo& g, const float* src, long src_pitch, float* It, float* Gx, float* Gy,
                              hipStream_t st) {

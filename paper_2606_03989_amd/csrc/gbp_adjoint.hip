@@ -10,12 +10,13 @@
 //   k_adj_update       reverse of the update at every pixel: cotangents of its
 //                      four new messages (Mb, 116 planes) and of its unary
 //                      information and point (Ub, 42 planes);
-//   k_adj_edges        every pixel, as the sender of its four outgoing
-//                      messages and the receiver of its four incoming ones:
-//                      cotangents of its marginals, of the residual's pose and
-//                      log-depth arguments, and of the stored messages the
-//                      sender subtracted (gathered from the neighbours' Mb, no
-//                      atomics);
+//   k_adj_edges        one lane per (pixel, direction): the pixel as the sender
+//                      of its outgoing message and the receiver of its incoming
+//                      one on that edge: cotangents of its marginals, of the
+//                      residual's pose and log-depth arguments, and of the
+//                      stored message the sender subtracted (gathered from the
+//                      neighbours' Mb, no atomics; the four directions of a
+//                      pixel are summed with lane shuffles);
 //   k_adj_belief       reverse of the marginals and of the unary factors:
 //                      completes Xb (cotangent of X) and accumulates the
 //                      per-pixel parameter gradients.
@@ -42,7 +43,7 @@ __device__ inline bool pixel_2d(const Geo& g, int& u, int& v) {
 
 // reverse of the update (k_pf_update): belief from the unary and the new
 // messages, mean m, relinearisation, transport of the messages
-__global__ __launch_bounds__(256) void k_adj_update(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
+__global__ __launch_bounds__(256, 2) void k_adj_update(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
                                                     const double* __restrict__ M, const float* __restrict__ Xb,
                                                     double* __restrict__ Mb, double* __restrict__ Ub) {
     int u, v;
@@ -154,36 +155,36 @@ __global__ __launch_bounds__(256) void k_adj_update(Geo g, Strengths s, Inputs i
     ub[UB_ELL * pl] = ellnb;
 }
 
-// reverse of the message step (k_pf_messages) at every pixel j, as receiver
-// (residual of its incoming messages) and as sender (its marginals and the
-// stored messages it subtracted). Writes the sender part of j's message-slot
-// cotangents to Xbo and the marginal / perturbation cotangents to Eb.
+// reverse of the message step (k_pf_messages), one lane per (pixel j,
+// direction d): j as the receiver of the message in its slot d (residual
+// cotangent) and as the sender of the message into its neighbour in direction
+// d (its marginals and the stored message it subtracted). The four lanes of a
+// pixel are adjacent; their contributions to j's marginal and perturbation
+// cotangents are summed with lane shuffles and written by the d = 0 lane.
+// Writes the sender part of j's slot-d cotangent to Xbo.
 __global__ __launch_bounds__(256) void k_adj_edges(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
                                                    const double* __restrict__ marg, const double* __restrict__ M,
                                                    const double* __restrict__ Mb, float* __restrict__ Xbo,
                                                    double* __restrict__ Eb, double* __restrict__ gN) {
-    int u, v;
-    if (!pixel_2d(g, u, v)) return;
-    const long pj = pix_of(g, u, v);
+    const int d = threadIdx.x & 3;
+    const int u = blockIdx.x * (blockDim.x >> 2) + (threadIdx.x >> 2);
+    const int v = blockIdx.y;
+    // every lane of a pixel takes part in the shuffles; lanes past the row end
+    // work on a clamped copy and write nothing
+    const bool inside = u < g.W;
+    const int uc = inside ? u : g.W - 1;
+    const long pj = pix_of(g, uc, v);
     const long pl = g.plane;
-    double tau[6], ell, R[9], t[3];
-    load_point(X, g, pj, tau, ell);
-    se3_exp(tau, R, t);
-    double Pb[21], pb[6], epsb[6];
+    double acc[37];   // P_bar 21, p_bar 6, D_bar, dv_bar, eps_bar 6, ell_bar, lamN_bar
 #pragma unroll
-    for (int k = 0; k < 21; ++k) Pb[k] = 0.0;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) pb[k] = epsb[k] = 0.0;
-    double Db = 0.0, dvb = 0.0, ellb = 0.0, lamNb = 0.0;
-    for (int d = 0; d < 4; ++d) {
-        float* xo = Xbo + (long)(P_MID + d * MID_STRIDE) * pl + pj;
-        float* xn = Xbo + (long)(P_MN + 2 * d) * pl + pj;
-        int nu, nv;
-        if (!neighbour(g, u, v, d, nu, nv)) {
-            for (int k = 0; k < MID_STRIDE; ++k) xo[k * pl] = 0.0f;
-            xn[0] = xn[pl] = 0.0f;
-            continue;
-        }
+    for (int k = 0; k < 37; ++k) acc[k] = 0.0;
+    float* xo = Xbo + (long)(P_MID + d * MID_STRIDE) * pl + pj;
+    float* xn = Xbo + (long)(P_MN + 2 * d) * pl + pj;
+    int nu, nv;
+    if (neighbour(g, uc, v, d, nu, nv)) {
+        double tau[6], ell, R[9], t[3];
+        load_point(X, g, pj, tau, ell);
+        se3_exp(tau, R, t);
         const long pi = pix_of(g, nu, nv);
         const int o = opposite(d);
         const double* Mj = M + (long)d * MSG_STRIDE * pl + pj;
@@ -197,8 +198,7 @@ __global__ __launch_bounds__(256) void k_adj_edges(Geo g, Strengths s, Inputs in
         se3_exp(ti, Ri, tri);
         se3_between(Ri, tri, R, t, r);
         // eta_new = h - Lp r on both sides: receiver r_bar = -Lp_j eb_j, sender
-        // r_bar = -Lp_i eb_i with d(-r)/d(eps_j) = -Jr(r)^-1 ... combined:
-        //   eps_j += Jr(r)^-T (Lp_i eb_i - Lp_j eb_j)
+        // r_bar = -Lp_i eb_i with d(-r) = -d r, so eps_j += Jr(r)^-T (Lp_i eb_i - Lp_j eb_j)
         double rb[6];
         {
             double Lam[21], e[6], y1[6], y2[6];
@@ -215,10 +215,7 @@ __global__ __launch_bounds__(256) void k_adj_edges(Geo g, Strengths s, Inputs in
 #pragma unroll
             for (int a = 0; a < 6; ++a) rb[a] = y2[a] - y1[a];
         }
-        double e6[6];
-        jac_invT_apply(r, -1.0, rb, e6);
-#pragma unroll
-        for (int k = 0; k < 6; ++k) epsb[k] += e6[k];
+        jac_invT_apply(r, -1.0, rb, acc + 29);
 
         // sender: the partial of the message into i from j's variable-to-factor
         // message (j's marginal minus j's stored message from this factor)
@@ -237,14 +234,14 @@ __global__ __launch_bounds__(256) void k_adj_edges(Geo g, Strengths s, Inputs in
         sym_outer_acc6(Lpb, hb, r, 1.0);
         identity_partial_adjoint(s.lamR, V, vv, Lpb, hb, Vb, vb);
 #pragma unroll
-        for (int k = 0; k < 21; ++k) {
-            Pb[k] += Vb[k];
-            xo[(6 + k) * pl] = (float)(-Vb[k]);
-        }
+        for (int k = 0; k < 21; ++k) acc[k] = Vb[k];
 #pragma unroll
-        for (int a = 0; a < 6; ++a) {
-            pb[a] += vb[a];
-            xo[a * pl] = (float)(-vb[a]);
+        for (int a = 0; a < 6; ++a) acc[21 + a] = vb[a];
+        if (inside) {
+#pragma unroll
+            for (int k = 0; k < 21; ++k) xo[(6 + k) * pl] = (float)(-Vb[k]);
+#pragma unroll
+            for (int a = 0; a < 6; ++a) xo[a * pl] = (float)(-vb[a]);
         }
 
         // normal-integration factor of the edge
@@ -253,33 +250,46 @@ __global__ __launch_bounds__(256) void k_adj_edges(Geo g, Strengths s, Inputs in
         if (s.lamN > 0.0 && normal_residual(g, in, pj, pi, d, ell, elli, rn_j)) {
             normal_residual(g, in, pi, pj, o, elli, ell, rn_i);
             // ne_new = h - lp rn: receiver j and sender j (rn_i depends on ell_j with -1)
-            ellb += -Mj[28 * pl] * Mbj[27 * pl] + Mi[28 * pl] * Mbi[27 * pl];
+            acc[35] = -Mj[28 * pl] * Mbj[27 * pl] + Mi[28 * pl] * Mbi[27 * pl];
             const double neb = Mbi[27 * pl], nlb = Mbi[28 * pl];
             const double ls = marg[27L * pl + pj] - (double)X[(long)(P_MN + 2 * d + 1) * pl + pj];
             const double vs = marg[28L * pl + pj] - (double)X[(long)(P_MN + 2 * d) * pl + pj];
             double lsb, vsb, lnb;
             normal_partial_adjoint(s.lamN, ls, vs, nlb - neb * rn_i, neb, lsb, vsb, lnb);
-            Db += lsb;
-            dvb += vsb;
-            lamNb += lnb;
+            acc[27] = lsb;
+            acc[28] = vsb;
+            acc[36] = lnb;
             nsb = -vsb;
             nlsb = -lsb;
         }
-        xn[0] = (float)nsb;
-        xn[pl] = (float)nlsb;
+        if (inside) {
+            xn[0] = (float)nsb;
+            xn[pl] = (float)nlsb;
+        }
+    } else if (inside) {
+        for (int k = 0; k < MID_STRIDE; ++k) xo[k * pl] = 0.0f;
+        xn[0] = xn[pl] = 0.0f;
     }
-    double* eb = Eb + pj;
+    // sum over the four directions of the pixel (lanes 4q .. 4q + 3)
 #pragma unroll
-    for (int k = 0; k < 21; ++k) eb[(EB_P + k) * pl] = Pb[k];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        eb[(EB_PV + k) * pl] = pb[k];
-        eb[(EB_EPS + k) * pl] = epsb[k];
+    for (int k = 0; k < 37; ++k) {
+        acc[k] += __shfl_xor(acc[k], 1, 4);
+        acc[k] += __shfl_xor(acc[k], 2, 4);
     }
-    eb[EB_D * pl] = Db;
-    eb[EB_DV * pl] = dvb;
-    eb[EB_ELL * pl] = ellb;
-    gN[pj] += lamNb;
+    if (d == 0 && inside) {
+        double* eb = Eb + pj;
+#pragma unroll
+        for (int k = 0; k < 21; ++k) eb[(EB_P + k) * pl] = acc[k];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            eb[(EB_PV + k) * pl] = acc[21 + k];
+            eb[(EB_EPS + k) * pl] = acc[29 + k];
+        }
+        eb[EB_D * pl] = acc[27];
+        eb[EB_DV * pl] = acc[28];
+        eb[EB_ELL * pl] = acc[35];
+        gN[pj] += acc[36];
+    }
 }
 
 // reverse of the marginals and of the unary factors; completes Xbo
@@ -427,7 +437,9 @@ hipError_t launch_adj_update(const Geo& g, const Strengths& s, const Inputs& in,
 
 hipError_t launch_adj_edges(const Geo& g, const Strengths& s, const Inputs& in, const float* X, const double* marg,
                             const double* M, const double* Mb, float* Xbo, double* Eb, double* gN, hipStream_t st) {
-    hipLaunchKernelGGL(k_adj_edges, adj_grid(g), kAdjBlock, 0, st, g, s, in, X, marg, M, Mb, Xbo, Eb, gN);
+    // one lane per (pixel, direction): 64 pixels of a row per 256-lane workgroup
+    hipLaunchKernelGGL(k_adj_edges, dim3((g.W + 63) / 64, g.H), dim3(256), 0, st, g, s, in, X, marg, M, Mb, Xbo, Eb,
+                       gN);
     return hipGetLastError();
 }
 

@@ -18,14 +18,16 @@ hipError_t launch_keyframe_prep(const Geo& g, const float* img, const float* nor
 hipError_t launch_init_state(const Geo& g, float* X, float ell0, hipStream_t st);
 hipError_t launch_pf_iteration(const Geo& g, const Strengths& s, const Inputs& in, float* X, double* marg,
                                double* M, float* var_ll, float* valid, float beta, int* health, hipStream_t st);
-// the first two steps of a per-factor iteration (marginals, then the new
-// messages) without the update: X is left unchanged
-hipError_t launch_pf_marginals_messages(const Geo& g, const Strengths& s, const Inputs& in, const float* X,
-                                        double* marg, double* M, float* valid, int* health, hipStream_t st);
 hipError_t launch_fu_prologue(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* Y,
                               int* health, hipStream_t st);
 hipError_t launch_fu_iterate(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* Y,
                              bool final_pass, float* var_ll, float* valid, int* health, hipStream_t st);
+// one fused iteration X -> Y (prologue into tmp, final pass into Y) that also
+// writes the marginals (29 FP64 planes) and the new messages (116 FP64 planes)
+// of X, as the per-factor kernels compute them
+hipError_t launch_fu_step_tape(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* tmp,
+                               float* Y, double* marg, double* M, float* var_ll, float* valid, int* health,
+                               hipStream_t st);
 hipError_t launch_valid_only(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* valid,
                              hipStream_t st);
 int stats_blocks(const Geo& g);

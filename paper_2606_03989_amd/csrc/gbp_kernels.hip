@@ -51,11 +51,21 @@ __device__ inline bool update_and_transport(double L[28], double eta[7], double 
 // belief (L, eta) and its stored messages; written to the neighbour's slot
 __device__ inline void emit_partials(const Geo& g, const Strengths& s, const Inputs& in, int u, int v,
                                      const double L[28], const double eta[7], const float mid[4][27],
-                                     const float mn[4][2], float* __restrict__ Y, bool& ok) {
+                                     const float mn[4][2], float* __restrict__ Y, bool& ok,
+                                     double* __restrict__ marg_out = nullptr) {
     double P[21], p[6], D, dv;
     pose_marginal(L, eta, P, p);
     ok = depth_marginal(L, eta, D, dv) && ok;
     const long pi = pix_of(g, u, v);
+    if (marg_out) {
+        // the marginals in the per-factor layout (k_pf_linearise): P 21, p 6, D, dv
+#pragma unroll
+        for (int k = 0; k < 21; ++k) marg_out[(long)k * g.plane + pi] = P[k];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) marg_out[(long)(21 + k) * g.plane + pi] = p[k];
+        marg_out[27L * g.plane + pi] = D;
+        marg_out[28L * g.plane + pi] = dv;
+    }
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
         int nu, nv;
@@ -112,7 +122,7 @@ __device__ inline void accumulate_message(double L[28], double eta[7], const dou
 __device__ inline void complete_partials(const Geo& g, const Strengths& s, const Inputs& in,
                                          const float* __restrict__ X, int u, int v, const double R[9],
                                          const double t[3], double ell, double L[28], double eta[7],
-                                         float mid[4][27], float mn[4][2]) {
+                                         float mid[4][27], float mn[4][2], double* __restrict__ M_out = nullptr) {
     const long pi = pix_of(g, u, v);
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
@@ -121,6 +131,9 @@ __device__ inline void complete_partials(const Geo& g, const Strengths& s, const
 #pragma unroll
             for (int k = 0; k < 27; ++k) mid[d][k] = 0.0f;
             mn[d][0] = mn[d][1] = 0.0f;
+            if (M_out)
+#pragma unroll
+                for (int k = 0; k < 29; ++k) M_out[(long)(d * 29 + k) * g.plane + pi] = 0.0;
             continue;
         }
         const long pj = pix_of(g, nu, nv);
@@ -149,6 +162,16 @@ __device__ inline void complete_partials(const Geo& g, const Strengths& s, const
             ne = (double)sn[0] - (double)nl * rn;
         }
         accumulate_message(L, eta, e6, part + 6, ne, nl, mid[d], mn[d]);
+        if (M_out) {
+            // the new message in the per-factor layout (k_pf_messages)
+            double* o = M_out + (long)(d * 29) * g.plane + pi;
+#pragma unroll
+            for (int a = 0; a < 6; ++a) o[a * g.plane] = e6[a];
+#pragma unroll
+            for (int k = 0; k < 21; ++k) o[(6 + k) * g.plane] = (double)part[6 + k];
+            o[27 * g.plane] = ne;
+            o[28 * g.plane] = (double)nl;
+        }
     }
 }
 
@@ -278,7 +301,7 @@ __global__ __launch_bounds__(256) void k_pf_linearise(Geo g, Strengths s, Inputs
 // marginals and the messages those neighbours hold from the shared factor.
 // Output (FP64 scratch, 29 planes per direction): identity eta(6), identity
 // Lambda(21, already at storage precision), normal eta, normal lambda.
-__global__ __launch_bounds__(256) void k_pf_messages(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
+__global__ __launch_bounds__(256, 2) void k_pf_messages(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
                                                      const double* __restrict__ marg, double* __restrict__ M,
                                                      float beta, int* __restrict__ health) {
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
@@ -396,7 +419,8 @@ __global__ __launch_bounds__(256) void k_pf_update(Geo g, Strengths s, Inputs in
 
 // prologue of one pixel: belief of the canonical state and the first partials
 __device__ __attribute__((always_inline)) inline void prologue_pixel(const Geo& g, const Strengths& s, const Inputs& in, const float* __restrict__ X,
-                                      float* __restrict__ Y, int* __restrict__ health, int u, int v) {
+                                      float* __restrict__ Y, int* __restrict__ health, int u, int v,
+                                      double* __restrict__ marg_out = nullptr) {
     const long p = pix_of(g, u, v);
     double tau[6], ell, R[9], t[3], L[28], eta[7];
     load_point(X, g, p, tau, ell);
@@ -406,7 +430,7 @@ __device__ __attribute__((always_inline)) inline void prologue_pixel(const Geo& 
     load_messages(X, g, p, mid, mn);
     add_messages(L, eta, mid, mn);
     bool ok = true;
-    emit_partials(g, s, in, u, v, L, eta, mid, mn, Y, ok);
+    emit_partials(g, s, in, u, v, L, eta, mid, mn, Y, ok, marg_out);
     store_point(Y, g, p, tau, ell);
     if (!ok) atomicOr(health, 1);
 }
@@ -417,14 +441,14 @@ __device__ __attribute__((always_inline)) inline void prologue_pixel(const Geo& 
 template <bool FINAL>
 __device__ __attribute__((always_inline)) inline void iterate_pixel(const Geo& g, const Strengths& s, const Inputs& in, const float* __restrict__ X,
                                      float* __restrict__ Y, float* __restrict__ var_ll, float* __restrict__ valid,
-                                     int* __restrict__ health, int u, int v) {
+                                     int* __restrict__ health, int u, int v, double* __restrict__ M_out = nullptr) {
     const long p = pix_of(g, u, v);
     double tau[6], ell, R[9], t[3], L[28], eta[7];
     load_point(X, g, p, tau, ell);
     se3_exp(tau, R, t);
     const bool val = unary_factors(g, s, in, u, v, tau, R, t, ell, L, eta);
     float mid[4][27], mn[4][2];
-    complete_partials(g, s, in, X, u, v, R, t, ell, L, eta, mid, mn);
+    complete_partials(g, s, in, X, u, v, R, t, ell, L, eta, mid, mn, M_out);
     double var;
     bool ok = update_and_transport(L, eta, tau, ell, mid, mn, var);
     round_point(tau, ell);
@@ -458,6 +482,28 @@ __global__ __launch_bounds__(256) void k_fu_iterate(Geo g, Strengths s, Inputs i
     const int v = blockIdx.y * blockDim.y + threadIdx.y;
     if (u >= g.W || v >= g.H) return;
     iterate_pixel<FINAL>(g, s, in, X, Y, var_ll, valid, health, u, v);
+}
+
+// the same passes for the reverse sweep's recompute: the prologue also writes
+// the marginals of its state, the final pass the new messages computed from
+// its source state (exactly the values of k_pf_linearise and k_pf_messages)
+__global__ __launch_bounds__(256) void k_fu_prologue_tape(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
+                                                          float* __restrict__ Y, double* __restrict__ marg,
+                                                          int* __restrict__ health) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y * blockDim.y + threadIdx.y;
+    if (u >= g.W || v >= g.H) return;
+    prologue_pixel(g, s, in, X, Y, health, u, v, marg);
+}
+
+__global__ __launch_bounds__(256) void k_fu_final_tape(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
+                                                       float* __restrict__ Y, double* __restrict__ M,
+                                                       float* __restrict__ var_ll, float* __restrict__ valid,
+                                                       int* __restrict__ health) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y * blockDim.y + threadIdx.y;
+    if (u >= g.W || v >= g.H) return;
+    iterate_pixel<true>(g, s, in, X, Y, var_ll, valid, health, u, v, M);
 }
 
 // ---------------------------------------------------------------------------
@@ -732,13 +778,6 @@ hipError_t launch_pf_iteration(const Geo& g, const Strengths& s, const Inputs& i
     return hipGetLastError();
 }
 
-hipError_t launch_pf_marginals_messages(const Geo& g, const Strengths& s, const Inputs& in, const float* X,
-                                        double* marg, double* M, float* valid, int* health, hipStream_t st) {
-    hipLaunchKernelGGL(k_pf_linearise, grid2d(g, kBlock), kBlock, 0, st, g, s, in, X, marg, valid, health);
-    hipLaunchKernelGGL(k_pf_messages, grid2d(g, kBlock), kBlock, 0, st, g, s, in, X, marg, M, 0.0f, health);
-    return hipGetLastError();
-}
-
 hipError_t launch_fu_prologue(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* Y,
                               int* health, hipStream_t st) {
     hipLaunchKernelGGL(k_fu_prologue, grid2d(g, kBlock), kBlock, 0, st, g, s, in, X, Y, health);
@@ -751,6 +790,14 @@ hipError_t launch_fu_iterate(const Geo& g, const Strengths& s, const Inputs& in,
         hipLaunchKernelGGL(k_fu_iterate<true>, grid2d(g, kBlock), kBlock, 0, st, g, s, in, X, Y, var_ll, valid, health);
     else
         hipLaunchKernelGGL(k_fu_iterate<false>, grid2d(g, kBlock), kBlock, 0, st, g, s, in, X, Y, var_ll, valid, health);
+    return hipGetLastError();
+}
+
+hipError_t launch_fu_step_tape(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* tmp,
+                               float* Y, double* marg, double* M, float* var_ll, float* valid, int* health,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_fu_prologue_tape, grid2d(g, kBlock), kBlock, 0, st, g, s, in, X, tmp, marg, health);
+    hipLaunchKernelGGL(k_fu_final_tape, grid2d(g, kBlock), kBlock, 0, st, g, s, in, tmp, Y, M, var_ll, valid, health);
     return hipGetLastError();
 }
 

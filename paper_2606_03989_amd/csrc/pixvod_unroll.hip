@@ -6,9 +6,9 @@
 // (per-factor and fused schedules are the same iteration bit for bit, so the
 // tape holds exactly the per-factor states).
 // Backward, for frames and segments in reverse: recompute the segment's
-// states from its checkpoint (one prologue + final pass per state), then for
-// each state from last to first recompute its marginals and new messages and
-// run the three reverse kernels.
+// states from its checkpoint, one prologue + final pass per state, which also
+// keep each state's marginals and new messages; then run the three reverse
+// kernels for each state from last to first.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -199,7 +199,8 @@ int pixvod_unroll_create(int H, int W, const pixvod_intrinsics* K, const pixvod_
               ualloc(&u->frames, N * (size_t)max_frames) && ualloc(&u->stage, N * 4) && ualloc(&u->X0, S) &&
               ualloc(&u->Xw[0], S) && ualloc(&u->Xw[1], S) && ualloc(&u->tape, S * (size_t)max_frames * spf) &&
               ualloc(&u->Xend, S) && ualloc(&u->seg, S * (size_t)ckpt_every) && ualloc(&u->var_ll, pl) &&
-              ualloc(&u->valid, pl) && ualloc(&u->marg, pl * MARG_PLANES) && ualloc(&u->M, pl * MSG_PLANES) &&
+              ualloc(&u->valid, pl) && ualloc(&u->marg, pl * MARG_PLANES * (size_t)ckpt_every) &&
+              ualloc(&u->M, pl * MSG_PLANES * (size_t)ckpt_every) &&
               ualloc(&u->Mb, pl * MSG_PLANES) && ualloc(&u->Ub, pl * UB_PLANES) && ualloc(&u->Eb, pl * EB_PLANES) &&
               ualloc(&u->Xb[0], S) && ualloc(&u->Xb[1], S) && ualloc(&u->gsig, pl) && ualloc(&u->gN, pl) &&
               ualloc(&u->gk, pl) && ualloc(&u->partial, (size_t)nb * 8) &&
@@ -359,17 +360,22 @@ int pixvod_unroll_backward(pixvod_unroll* u, const double* xi_bar, const float* 
         UHIP(launch_frame_prep(g, u->frames + N * f, u->W, u->It, u->Gx, u->Gy, u->stream));
         for (int sg = u->seg_per_frame - 1; sg >= 0; --sg) {
             const int len = seg_len(u, sg);
-            // states of the segment: seg[0] = checkpoint, seg[i] after i iterations
+            // states of the segment: seg[0] = checkpoint, seg[i] after i
+            // iterations; each recompute step also keeps the marginals and the
+            // new messages of its source state (the last step's result is not
+            // needed and goes to a work buffer)
             UHIP(hipMemcpyAsync(u->seg, ckpt(u, f, sg), S * sizeof(float), hipMemcpyDeviceToDevice, u->stream));
-            for (int i = 1; i < len; ++i) {
-                int rc = fused_run(u, g, s, in, u->seg + S * (i - 1), u->Xw[0], u->Xw[1], u->seg + S * i, 1);
-                if (rc) return rc;
+            for (int i = 0; i < len; ++i) {
+                float* dst = (i + 1 < len) ? u->seg + S * (i + 1) : u->Xw[1];
+                UHIP(launch_fu_step_tape(g, s, in, u->seg + S * i, u->Xw[0], dst, u->marg + pl * MARG_PLANES * i,
+                                         u->M + pl * MSG_PLANES * i, u->var_ll, u->valid, u->health, u->stream));
             }
             for (int i = len - 1; i >= 0; --i) {
                 const float* X = u->seg + S * i;
-                UHIP(launch_pf_marginals_messages(g, s, in, X, u->marg, u->M, u->valid, u->health, u->stream));
-                UHIP(launch_adj_update(g, s, in, X, u->M, u->Xb[cur], u->Mb, u->Ub, u->stream));
-                UHIP(launch_adj_edges(g, s, in, X, u->marg, u->M, u->Mb, u->Xb[cur ^ 1], u->Eb, u->gN, u->stream));
+                const double* marg = u->marg + pl * MARG_PLANES * i;
+                const double* M = u->M + pl * MSG_PLANES * i;
+                UHIP(launch_adj_update(g, s, in, X, M, u->Xb[cur], u->Mb, u->Ub, u->stream));
+                UHIP(launch_adj_edges(g, s, in, X, marg, M, u->Mb, u->Xb[cur ^ 1], u->Eb, u->gN, u->stream));
                 UHIP(launch_adj_belief(g, s, in, X, u->Ub, u->Eb, u->Xb[cur ^ 1], u->gsig, u->gk, u->stream));
                 cur ^= 1;
             }

@@ -16,11 +16,12 @@ struct PoseBar {
 };
 
 hipError_t launch_adj_update(const Geo& g, const Strengths& s, const Inputs& in, const float* X, const double* M,
-                             const float* Xb, double* Mb, double* Ub, hipStream_t st);
+                             const double* bel, const float* Xb, double* Mb, double* Ub, hipStream_t st);
 hipError_t launch_adj_edges(const Geo& g, const Strengths& s, const Inputs& in, const float* X, const double* marg,
                             const double* M, const double* Mb, float* Xbo, double* Eb, double* gN, hipStream_t st);
-hipError_t launch_adj_belief(const Geo& g, const Strengths& s, const Inputs& in, const float* X, const double* Ub,
-                             const double* Eb, float* Xbo, double* gsig, double* gk, hipStream_t st);
+hipError_t launch_adj_belief(const Geo& g, const Strengths& s, const Inputs& in, const float* X, const double* marg,
+                             const double* Ub, const double* Eb, float* Xbo, double* gsig, double* gk,
+                             hipStream_t st);
 hipError_t launch_adj_inject(const Geo& g, const float* Xend, float* Xb, const PoseBar& xb, const float* rhob,
                              hipStream_t st);
 int sum2_blocks(const Geo& g);

@@ -5,8 +5,9 @@
 // Reverse of one canonical iteration X -> X' (linearise + marginals, messages,
 // update + relinearise + transport; Sec. 3.4 and Sec. 4.1), given the
 // cotangent Xb' of X':
-//   forward recompute  marginals (29 planes) and new messages (116 planes) of X,
-//                      by the per-factor kernels;
+//   forward recompute  the fused passes that recompute X also keep its belief
+//                      and marginals (64 planes), its new messages (116) and
+//                      the belief of the update (35);
 //   k_adj_update       reverse of the update at every pixel: cotangents of its
 //                      four new messages (Mb, 116 planes) and of its unary
 //                      information and point (Ub, 42 planes);
@@ -44,8 +45,9 @@ __device__ inline bool pixel_2d(const Geo& g, int& u, int& v) {
 // reverse of the update (k_pf_update): belief from the unary and the new
 // messages, mean m, relinearisation, transport of the messages
 __global__ __launch_bounds__(256, 2) void k_adj_update(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
-                                                    const double* __restrict__ M, const float* __restrict__ Xb,
-                                                    double* __restrict__ Mb, double* __restrict__ Ub) {
+                                                    const double* __restrict__ M, const double* __restrict__ bel,
+                                                    const float* __restrict__ Xb, double* __restrict__ Mb,
+                                                    double* __restrict__ Ub) {
     int u, v;
     if (!pixel_2d(g, u, v)) return;
     const long p = pix_of(g, u, v);
@@ -53,19 +55,11 @@ __global__ __launch_bounds__(256, 2) void k_adj_update(Geo g, Strengths s, Input
     double tau[6], ell, R[9], t[3], L[28], eta[7];
     load_point(X, g, p, tau, ell);
     se3_exp(tau, R, t);
-    unary_factors(g, s, in, u, v, tau, R, t, ell, L, eta);
+    // the belief of the update (unary + new messages), kept by the recompute
 #pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        const double* md = M + (long)d * MSG_STRIDE * pl + p;
+    for (int k = 0; k < 28; ++k) L[k] = bel[(long)k * pl + p];
 #pragma unroll
-        for (int a = 0; a < 6; ++a) eta[a] += md[a * pl];
-#pragma unroll
-        for (int r = 0; r < 6; ++r)
-#pragma unroll
-            for (int c = r; c < 6; ++c) L[s7(r, c)] += md[(6 + s6(r, c)) * pl];
-        eta[6] += md[27 * pl];
-        L[s7(6, 6)] += md[28 * pl];
-    }
+    for (int k = 0; k < 7; ++k) eta[k] = bel[(long)(28 + k) * pl + p];
     double idg[7], m[7];
     chol7(L, idg);
 #pragma unroll
@@ -294,7 +288,8 @@ __global__ __launch_bounds__(256) void k_adj_edges(Geo g, Strengths s, Inputs in
 
 // reverse of the marginals and of the unary factors; completes Xbo
 __global__ __launch_bounds__(256) void k_adj_belief(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
-                                                    const double* __restrict__ Ub, const double* __restrict__ Eb,
+                                                    const double* __restrict__ marg, const double* __restrict__ Ub,
+                                                    const double* __restrict__ Eb,
                                                     float* __restrict__ Xbo, double* __restrict__ gsig,
                                                     double* __restrict__ gk) {
     int u, v;
@@ -304,12 +299,11 @@ __global__ __launch_bounds__(256) void k_adj_belief(Geo g, Strengths s, Inputs i
     double tau[6], ell, R[9], t[3], L[28], eta[7];
     load_point(X, g, p, tau, ell);
     se3_exp(tau, R, t);
-    unary_factors(g, s, in, u, v, tau, R, t, ell, L, eta);
-    {
-        float mid[4][27], mn[4][2];
-        load_messages(X, g, p, mid, mn);
-        add_messages(L, eta, mid, mn);
-    }
+    // the belief of the marginals (unary + stored messages), kept by the recompute
+#pragma unroll
+    for (int k = 0; k < 28; ++k) L[k] = marg[(long)(29 + k) * pl + p];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) eta[k] = marg[(long)(57 + k) * pl + p];
     const double* eb = Eb + p;
     double Pb[21], pb[6];
 #pragma unroll
@@ -430,8 +424,8 @@ static const dim3 kAdjBlock(64, 4);
 static dim3 adj_grid(const Geo& g) { return dim3((g.W + 63) / 64, (g.H + 3) / 4); }
 
 hipError_t launch_adj_update(const Geo& g, const Strengths& s, const Inputs& in, const float* X, const double* M,
-                             const float* Xb, double* Mb, double* Ub, hipStream_t st) {
-    hipLaunchKernelGGL(k_adj_update, adj_grid(g), kAdjBlock, 0, st, g, s, in, X, M, Xb, Mb, Ub);
+                             const double* bel, const float* Xb, double* Mb, double* Ub, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_update, adj_grid(g), kAdjBlock, 0, st, g, s, in, X, M, bel, Xb, Mb, Ub);
     return hipGetLastError();
 }
 
@@ -443,9 +437,10 @@ hipError_t launch_adj_edges(const Geo& g, const Strengths& s, const Inputs& in, 
     return hipGetLastError();
 }
 
-hipError_t launch_adj_belief(const Geo& g, const Strengths& s, const Inputs& in, const float* X, const double* Ub,
-                             const double* Eb, float* Xbo, double* gsig, double* gk, hipStream_t st) {
-    hipLaunchKernelGGL(k_adj_belief, adj_grid(g), kAdjBlock, 0, st, g, s, in, X, Ub, Eb, Xbo, gsig, gk);
+hipError_t launch_adj_belief(const Geo& g, const Strengths& s, const Inputs& in, const float* X, const double* marg,
+                             const double* Ub, const double* Eb, float* Xbo, double* gsig, double* gk,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_belief, adj_grid(g), kAdjBlock, 0, st, g, s, in, X, marg, Ub, Eb, Xbo, gsig, gk);
     return hipGetLastError();
 }
 

@@ -23,11 +23,12 @@ hipError_t launch_fu_prologue(const Geo& g, const Strengths& s, const Inputs& in
 hipError_t launch_fu_iterate(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* Y,
                              bool final_pass, float* var_ll, float* valid, int* health, hipStream_t st);
 // one fused iteration X -> Y (prologue into tmp, final pass into Y) that also
-// writes the marginals (29 FP64 planes) and the new messages (116 FP64 planes)
-// of X, as the per-factor kernels compute them
+// writes, as the per-factor kernels compute them, for X: the marginals (29
+// FP64 planes) followed by the belief they come from (35), the new messages
+// (116) and the belief of the update, unary + new messages (35)
 hipError_t launch_fu_step_tape(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* tmp,
-                               float* Y, double* marg, double* M, float* var_ll, float* valid, int* health,
-                               hipStream_t st);
+                               float* Y, double* marg, double* M, double* bel, float* var_ll, float* valid,
+                               int* health, hipStream_t st);
 hipError_t launch_valid_only(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* valid,
                              hipStream_t st);
 int stats_blocks(const Geo& g);

@@ -58,13 +58,18 @@ __device__ inline void emit_partials(const Geo& g, const Strengths& s, const Inp
     ok = depth_marginal(L, eta, D, dv) && ok;
     const long pi = pix_of(g, u, v);
     if (marg_out) {
-        // the marginals in the per-factor layout (k_pf_linearise): P 21, p 6, D, dv
+        // the marginals in the per-factor layout (k_pf_linearise): P 21, p 6,
+        // D, dv; then the belief they come from: L 28, eta 7
 #pragma unroll
         for (int k = 0; k < 21; ++k) marg_out[(long)k * g.plane + pi] = P[k];
 #pragma unroll
         for (int k = 0; k < 6; ++k) marg_out[(long)(21 + k) * g.plane + pi] = p[k];
         marg_out[27L * g.plane + pi] = D;
         marg_out[28L * g.plane + pi] = dv;
+#pragma unroll
+        for (int k = 0; k < 28; ++k) marg_out[(long)(29 + k) * g.plane + pi] = L[k];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) marg_out[(long)(57 + k) * g.plane + pi] = eta[k];
     }
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
@@ -441,7 +446,8 @@ __device__ __attribute__((always_inline)) inline void prologue_pixel(const Geo& 
 template <bool FINAL>
 __device__ __attribute__((always_inline)) inline void iterate_pixel(const Geo& g, const Strengths& s, const Inputs& in, const float* __restrict__ X,
                                      float* __restrict__ Y, float* __restrict__ var_ll, float* __restrict__ valid,
-                                     int* __restrict__ health, int u, int v, double* __restrict__ M_out = nullptr) {
+                                     int* __restrict__ health, int u, int v, double* __restrict__ M_out = nullptr,
+                                     double* __restrict__ bel_out = nullptr) {
     const long p = pix_of(g, u, v);
     double tau[6], ell, R[9], t[3], L[28], eta[7];
     load_point(X, g, p, tau, ell);
@@ -449,6 +455,13 @@ __device__ __attribute__((always_inline)) inline void iterate_pixel(const Geo& g
     const bool val = unary_factors(g, s, in, u, v, tau, R, t, ell, L, eta);
     float mid[4][27], mn[4][2];
     complete_partials(g, s, in, X, u, v, R, t, ell, L, eta, mid, mn, M_out);
+    if (bel_out) {
+        // the belief of the update (unary + new messages): L 28, eta 7
+#pragma unroll
+        for (int k = 0; k < 28; ++k) bel_out[(long)k * g.plane + p] = L[k];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) bel_out[(long)(28 + k) * g.plane + p] = eta[k];
+    }
     double var;
     bool ok = update_and_transport(L, eta, tau, ell, mid, mn, var);
     round_point(tau, ell);
@@ -485,8 +498,9 @@ __global__ __launch_bounds__(256) void k_fu_iterate(Geo g, Strengths s, Inputs i
 }
 
 // the same passes for the reverse sweep's recompute: the prologue also writes
-// the marginals of its state, the final pass the new messages computed from
-// its source state (exactly the values of k_pf_linearise and k_pf_messages)
+// the belief of its state and its marginals, the final pass the new messages
+// computed from its source state and the belief they form with the unary
+// factors (exactly the values of k_pf_linearise, k_pf_messages, k_pf_update)
 __global__ __launch_bounds__(256) void k_fu_prologue_tape(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
                                                           float* __restrict__ Y, double* __restrict__ marg,
                                                           int* __restrict__ health) {
@@ -498,12 +512,12 @@ __global__ __launch_bounds__(256) void k_fu_prologue_tape(Geo g, Strengths s, In
 
 __global__ __launch_bounds__(256) void k_fu_final_tape(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
                                                        float* __restrict__ Y, double* __restrict__ M,
-                                                       float* __restrict__ var_ll, float* __restrict__ valid,
-                                                       int* __restrict__ health) {
+                                                       double* __restrict__ bel, float* __restrict__ var_ll,
+                                                       float* __restrict__ valid, int* __restrict__ health) {
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
     const int v = blockIdx.y * blockDim.y + threadIdx.y;
     if (u >= g.W || v >= g.H) return;
-    iterate_pixel<true>(g, s, in, X, Y, var_ll, valid, health, u, v, M);
+    iterate_pixel<true>(g, s, in, X, Y, var_ll, valid, health, u, v, M, bel);
 }
 
 // ---------------------------------------------------------------------------
@@ -794,10 +808,11 @@ hipError_t launch_fu_iterate(const Geo& g, const Strengths& s, const Inputs& in,
 }
 
 hipError_t launch_fu_step_tape(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* tmp,
-                               float* Y, double* marg, double* M, float* var_ll, float* valid, int* health,
-                               hipStream_t st) {
+                               float* Y, double* marg, double* M, double* bel, float* var_ll, float* valid,
+                               int* health, hipStream_t st) {
     hipLaunchKernelGGL(k_fu_prologue_tape, grid2d(g, kBlock), kBlock, 0, st, g, s, in, X, tmp, marg, health);
-    hipLaunchKernelGGL(k_fu_final_tape, grid2d(g, kBlock), kBlock, 0, st, g, s, in, tmp, Y, M, var_ll, valid, health);
+    hipLaunchKernelGGL(k_fu_final_tape, grid2d(g, kBlock), kBlock, 0, st, g, s, in, tmp, Y, M, bel, var_ll, valid,
+                       health);
     return hipGetLastError();
 }
 

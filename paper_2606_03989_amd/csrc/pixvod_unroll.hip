@@ -25,7 +25,8 @@ using namespace pv;
 
 namespace {
 constexpr int MSG_PLANES = 116;  // 4 x (eta 6, Lambda 21, normal eta, normal lambda)
-constexpr int MARG_PLANES = 29;  // pose marginal 21 + 6, depth marginal 2
+constexpr int MARG_PLANES = 64;  // pose marginal 21 + 6, depth marginal 2, their belief 28 + 7
+constexpr int BEL_PLANES = 35;   // belief of the update: 28 + 7
 constexpr int UB_PLANES = 42;
 constexpr int EB_PLANES = 36;
 }  // namespace
@@ -42,7 +43,7 @@ struct pixvod_unroll {
     float *frames = nullptr, *stage = nullptr;
     float *X0 = nullptr, *Xw[2] = {nullptr, nullptr}, *tape = nullptr, *Xend = nullptr, *seg = nullptr;
     float *var_ll = nullptr, *valid = nullptr;
-    double *marg = nullptr, *M = nullptr, *Mb = nullptr, *Ub = nullptr, *Eb = nullptr;
+    double *marg = nullptr, *M = nullptr, *bel = nullptr, *Mb = nullptr, *Ub = nullptr, *Eb = nullptr;
     float* Xb[2] = {nullptr, nullptr};
     double *gsig = nullptr, *gN = nullptr, *gk = nullptr;
     double *partial = nullptr, *stats = nullptr, *h_stats = nullptr;
@@ -118,7 +119,7 @@ static bool ualloc(T** p, size_t n) {
 
 static void urelease(pixvod_unroll* u) {
     void* bufs[] = {u->Is, u->cxt, u->cyt, u->sig, u->It, u->Gx, u->Gy, u->frames, u->stage, u->X0, u->Xw[0],
-                    u->Xw[1], u->tape, u->Xend, u->seg, u->var_ll, u->valid, u->marg, u->M, u->Mb, u->Ub, u->Eb,
+                    u->Xw[1], u->tape, u->Xend, u->seg, u->var_ll, u->valid, u->marg, u->M, u->bel, u->Mb, u->Ub, u->Eb,
                     u->Xb[0], u->Xb[1], u->gsig, u->gN, u->gk, u->partial, u->stats, u->health};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -201,6 +202,7 @@ int pixvod_unroll_create(int H, int W, const pixvod_intrinsics* K, const pixvod_
               ualloc(&u->Xend, S) && ualloc(&u->seg, S * (size_t)ckpt_every) && ualloc(&u->var_ll, pl) &&
               ualloc(&u->valid, pl) && ualloc(&u->marg, pl * MARG_PLANES * (size_t)ckpt_every) &&
               ualloc(&u->M, pl * MSG_PLANES * (size_t)ckpt_every) &&
+              ualloc(&u->bel, pl * BEL_PLANES * (size_t)ckpt_every) &&
               ualloc(&u->Mb, pl * MSG_PLANES) && ualloc(&u->Ub, pl * UB_PLANES) && ualloc(&u->Eb, pl * EB_PLANES) &&
               ualloc(&u->Xb[0], S) && ualloc(&u->Xb[1], S) && ualloc(&u->gsig, pl) && ualloc(&u->gN, pl) &&
               ualloc(&u->gk, pl) && ualloc(&u->partial, (size_t)nb * 8) &&
@@ -368,15 +370,18 @@ int pixvod_unroll_backward(pixvod_unroll* u, const double* xi_bar, const float* 
             for (int i = 0; i < len; ++i) {
                 float* dst = (i + 1 < len) ? u->seg + S * (i + 1) : u->Xw[1];
                 UHIP(launch_fu_step_tape(g, s, in, u->seg + S * i, u->Xw[0], dst, u->marg + pl * MARG_PLANES * i,
-                                         u->M + pl * MSG_PLANES * i, u->var_ll, u->valid, u->health, u->stream));
+                                         u->M + pl * MSG_PLANES * i, u->bel + pl * BEL_PLANES * i, u->var_ll,
+                                         u->valid, u->health, u->stream));
             }
             for (int i = len - 1; i >= 0; --i) {
                 const float* X = u->seg + S * i;
                 const double* marg = u->marg + pl * MARG_PLANES * i;
                 const double* M = u->M + pl * MSG_PLANES * i;
-                UHIP(launch_adj_update(g, s, in, X, M, u->Xb[cur], u->Mb, u->Ub, u->stream));
+                const double* bel = u->bel + pl * BEL_PLANES * i;
+                UHIP(launch_adj_update(g, s, in, X, M, bel, u->Xb[cur], u->Mb, u->Ub, u->stream));
                 UHIP(launch_adj_edges(g, s, in, X, marg, M, u->Mb, u->Xb[cur ^ 1], u->Eb, u->gN, u->stream));
-                UHIP(launch_adj_belief(g, s, in, X, u->Ub, u->Eb, u->Xb[cur ^ 1], u->gsig, u->gk, u->stream));
+                UHIP(launch_adj_belief(g, s, in, X, marg, u->Ub, u->Eb, u->Xb[cur ^ 1], u->gsig, u->gk,
+                                       u->stream));
                 cur ^= 1;
             }
         }

@@ -24,3 +24,4 @@ from .scenes import (  # noqa: F401
     SEQUENCE_CONFIGS,
     batch_resolution,
 )
+from .noise import PPA_MILD, PPA_STRONG, SensorNoise, degrade, render_noisy_frame  # noqa: F401

@@ -139,3 +139,17 @@ def make_unrolled_oracle(w, n_iters: int):
     from oracle.gradient import UnrolledOracle
     return UnrolledOracle(w["cam"], w["I_s"], w["N_s"], w["frames"], n_iters, w["sigma_map"], w["sigma_N"],
                           w["huber_k"], **w["kw"])
+
+
+def noisy_sequence_workload(name: str, n_frames: int, theta):
+    """A sequence workload whose keyframe and target frames go through the
+    sensor-noise model instead of the sequence's Gaussian pixel noise."""
+    from synth.noise import render_noisy_frame
+    cfg = SEQUENCE_CONFIGS[name]
+    scene, cam = make_sequence_scene(cfg)
+    poses = sequence_poses(cfg)
+    I0, D0, N0 = render_noisy_frame(cfg, scene, cam, poses, 0, theta, keyframe=True)
+    frames = [render_noisy_frame(cfg, scene, cam, poses, f, theta)[0] for f in range(1, n_frames + 1)]
+    iters = {"ppa256": 20, "vga": 20, "diff320": 30}[name]
+    return dict(cam=cam, I_s=I0, N_s=N0, frames=frames, iters=iters, kw=dict(SEQ_PARAMS[name]), depth0=D0,
+                poses=poses)

@@ -146,6 +146,30 @@ def test_ppa256_teacher_forced_frames():
         _assert_frame(rg, ro, f"ppa256 frame {k + 1} teacher-forced")
 
 
+@pytest.mark.parametrize("setting", ["mild", "strong"])
+def test_teacher_forced_iterations_sensor_noise(setting):
+    # keyframe and frame through the Poisson-Gaussian sensor model (App. D.1).
+    # Free-running comparisons are not meaningful here: a one-ulp change of the
+    # frame moves the oracle's own frame-1 pose by 1e-5 (mild) to 3e-5 (strong),
+    # so every iteration is compared from the same state
+    from parity import noisy_sequence_workload
+    from synth import PPA_MILD, PPA_STRONG
+    w = noisy_sequence_workload("ppa256", 1, PPA_MILD if setting == "mild" else PPA_STRONG)
+    t = make_tracker(w, 0)
+    o = make_oracle(w)
+    t.track(w["frames"][0], 0)
+    o.set_frame(w["frames"][0])
+    worst = 0.0
+    for it in range(w["iters"]):
+        o.set_state(to_oracle(t.get_state()))
+        t.iterate(1)
+        o.iterate(1)
+        q = float(np.percentile(_plane_errors(t.get_state(), from_oracle(o.get_state())), 99.9))
+        worst = max(worst, q)
+        assert q <= 1e-5, f"{setting} iteration {it}: p99.9 {q:.2e}"
+    print(f"ppa256 {setting} sensor noise, teacher-forced 20 iterations: worst p99.9 {worst:.2e}", flush=True)
+
+
 def test_vga_frame_1():
     w = sequence_workload("vga", 1)
     t, o, out = _run_both(w, 0)

@@ -148,6 +148,20 @@ int pixvod_set_sigma_map(pixvod_ctx* ctx, const float* sigma_D_map, int where);
 int pixvod_track(pixvod_ctx* ctx, const float* frame, int where, int n_iters,
                  pixvod_track_out* out);
 
+/* Prior means (Eq. prior; the log-depth prior of Sec. 3.3). xi: the pose mean
+ * of every pixel's prior factor (6 doubles, host; NULL keeps the current one);
+ * log_depth: per-pixel log-depth prior means (H*W floats at `where`; NULL keeps
+ * the current ones, initially params.prior_log_depth everywhere). A new
+ * keyframe returns the pose mean to params.prior_xi and keeps the log-depth
+ * means. */
+int pixvod_set_prior(pixvod_ctx* ctx, const double xi[6], const float* log_depth, int where);
+
+/* Temporal priors (motion continuity and depth propagation, Sec. 3.3): the
+ * last tracked frame's pose estimate and the current per-pixel log-depths
+ * become the prior means for the next frames. ESTATE before the first frame
+ * tracked on the current keyframe. */
+int pixvod_set_prior_from_state(pixvod_ctx* ctx);
+
 /* Runs n_iters iterations on the last staged frame without per-frame
  * bookkeeping (benchmarks and tests). */
 int pixvod_iterate(pixvod_ctx* ctx, int n_iters);

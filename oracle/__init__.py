@@ -57,6 +57,8 @@ def lib() -> C.CDLL:
         L.or_destroy.argtypes = [C.c_void_p]
         L.or_default_config.argtypes = [C.POINTER(OrConfig)]
         L.or_set_sigma_D_map.argtypes = [C.c_void_p, dp]
+        L.or_set_prior.argtypes = [C.c_void_p, dp, dp]
+        L.or_set_prior_from_state.argtypes = [C.c_void_p]
         L.or_set_keyframe.argtypes = [C.c_void_p, fp, fp]
         L.or_track.argtypes = [C.c_void_p, fp, C.c_int, C.POINTER(OrTrackOut), dp, dp]
         L.or_iterate.argtypes = [C.c_void_p, C.c_int]
@@ -196,6 +198,16 @@ class Oracle:
         else:
             s = np.ascontiguousarray(sig, dtype=np.float64).reshape(self.N)
             lib().or_set_sigma_D_map(self._h, _dp(s))
+
+    def set_prior(self, xi=None, log_depth=None):
+        """Prior means: pose xi (6) and per-pixel log-depths (H x W); None keeps them."""
+        x = None if xi is None else np.ascontiguousarray(xi, dtype=np.float64)
+        d = None if log_depth is None else np.ascontiguousarray(log_depth, dtype=np.float64).reshape(self.N)
+        lib().or_set_prior(self._h, None if x is None else _dp(x), None if d is None else _dp(d))
+
+    def set_prior_from_state(self):
+        """Temporal priors: the current mean pose and log-depths become the prior means."""
+        lib().or_set_prior_from_state(self._h)
 
     def set_keyframe(self, img, normals):
         i = np.ascontiguousarray(img, dtype=np.float32).reshape(self.N)

@@ -146,7 +146,8 @@ class Problem:
         self.lamN = 0.0 if math.isinf(sigma_N) else sigma_N ** -2
         self.k = huber_k
         self.prior_xi = np.zeros(6) if prior_xi is None else np.asarray(prior_xi, dtype=np.float64)
-        self.prior_ell = prior_log_depth
+        # scalar or per-pixel (H x W) log-depth prior mean
+        self.prior_ell = np.broadcast_to(np.asarray(prior_log_depth, dtype=np.float64), (H, W)).reshape(-1)
 
     @property
     def N(self):
@@ -168,12 +169,12 @@ class Problem:
         kap = huber_kappa(abs(r) * math.sqrt(lamD), self.k)
         return True, r, J, float(kap * lamD)
 
-    def prior(self, tau, ell):
+    def prior(self, tau, ell, i: int = 0):
         rp = log_se3(np.linalg.inv(exp_se3(self.prior_xi)) @ exp_se3(tau))
         J = np.zeros((7, 7))
         J[:6, :6] = prior_jac(rp)
         J[6, 6] = 1.0
-        return np.concatenate([rp, [ell - self.prior_ell]]), J
+        return np.concatenate([rp, [ell - self.prior_ell[i]]]), J
 
     def edges(self):
         """Undirected edges (a, b, horizontal) with a the left/upper pixel."""
@@ -201,7 +202,7 @@ class Problem:
                 nvalid += 1
                 L[s, s] += wgt * np.outer(J, J)
                 h[s] -= wgt * J * r
-            rp, Jp = self.prior(tau[i], ell[i])
+            rp, Jp = self.prior(tau[i], ell[i], i)
             L[s, s] += self.lamP * Jp.T @ Jp
             h[s] -= self.lamP * Jp.T @ rp
         for (a, b, horiz) in self.edges():

@@ -32,6 +32,7 @@ struct or_ctx {
     double *I_s, *cxt, *cyt;           /* keyframe image, normal targets */
     double *I_t, *Gx, *Gy;             /* target frame and its gradients */
     double *sigD;                      /* per-pixel photometric sigma */
+    double *prior_ell;                 /* per-pixel log-depth prior mean */
     double *tau, *ell;                 /* linearisation points */
     g7 *msg, *newmsg;                  /* 8 stored f2v messages per pixel */
     g7 *unary, *belief;
@@ -394,7 +395,7 @@ static int unary_at(const or_ctx* ctx, int i, double eta[7], double lam[49], int
         add_outer(lam, eta, row, rp[k], lamP);
     }
     double row6[7] = {0, 0, 0, 0, 0, 0, 1.0};
-    add_outer(lam, eta, row6, ell - c->prior_log_depth, lamP);
+    add_outer(lam, eta, row6, ell - ctx->prior_ell[i], lamP);
     return 0;
 }
 
@@ -495,6 +496,7 @@ or_ctx* or_create(const or_config* cfg) {
     x->Gx = calloc(N, sizeof(double));
     x->Gy = calloc(N, sizeof(double));
     x->sigD = calloc(N, sizeof(double));
+    x->prior_ell = calloc(N, sizeof(double));
     x->tau = calloc(6 * N, sizeof(double));
     x->ell = calloc(N, sizeof(double));
     x->msg = calloc(8 * N, sizeof(g7));
@@ -506,6 +508,7 @@ or_ctx* or_create(const or_config* cfg) {
     x->valid = calloc(N, sizeof(int));
     for (size_t i = 0; i < N; ++i) {
         x->sigD[i] = cfg->sigma_D;
+        x->prior_ell[i] = cfg->prior_log_depth;
         x->ell[i] = -log(cfg->init_inv_depth);
         x->var_ll[i] = NAN;
     }
@@ -517,7 +520,7 @@ or_ctx* or_create(const or_config* cfg) {
 void or_destroy(or_ctx* x) {
     if (!x) return;
     free(x->I_s); free(x->cxt); free(x->cyt); free(x->I_t); free(x->Gx); free(x->Gy);
-    free(x->sigD); free(x->tau); free(x->ell); free(x->msg); free(x->newmsg);
+    free(x->sigD); free(x->prior_ell); free(x->tau); free(x->ell); free(x->msg); free(x->newmsg);
     free(x->unary); free(x->belief); free(x->mean); free(x->var_ll); free(x->valid);
     free(x);
 }
@@ -903,6 +906,30 @@ int or_get_normal_targets(const or_ctx* x, double* cx_out, double* cy_out) {
     return 0;
 }
 
+/* prior factor means, Eq. (prior) and the log-depth prior of Sec. 3.3: the
+ * pose mean for every pixel and, if given, a per-pixel log-depth mean (NULL
+ * keeps the current ones). Temporal priors carry the previous frame's
+ * estimates forward this way. */
+int or_set_prior(or_ctx* x, const double xi[6], const double* log_depth) {
+    if (!x) return -1;
+    if (xi)
+        for (int k = 0; k < 6; ++k) x->cfg.prior_xi[k] = xi[k];
+    if (log_depth) memcpy(x->prior_ell, log_depth, sizeof(double) * (size_t)x->N);
+    return 0;
+}
+
+/* the pose estimate of the last tracked frame (mean of the per-pixel poses)
+ * and the current log-depths become the prior means */
+int or_set_prior_from_state(or_ctx* x) {
+    if (!x) return -1;
+    double m[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = 0; i < x->N; ++i)
+        for (int k = 0; k < 6; ++k) m[k] += x->tau[6 * (size_t)i + k];
+    for (int k = 0; k < 6; ++k) x->cfg.prior_xi[k] = m[k] / (double)x->N;
+    memcpy(x->prior_ell, x->ell, sizeof(double) * (size_t)x->N);
+    return 0;
+}
+
 int or_get_gradients(const or_ctx* x, double* gx, double* gy) {
     memcpy(gx, x->Gx, sizeof(double) * (size_t)x->N);
     memcpy(gy, x->Gy, sizeof(double) * (size_t)x->N);
@@ -939,7 +966,7 @@ double or_energy(const or_ctx* x) {
         mat_mul(4, 4, 4, Tpi, Tt, Tr);
         or_se3_log(Tr, rp);
         for (int k = 0; k < 6; ++k) E += 0.5 * lamP * rp[k] * rp[k];
-        double dl = x->ell[i] - c->prior_log_depth;
+        double dl = x->ell[i] - x->prior_ell[i];
         E += 0.5 * lamP * dl * dl;
         /* each edge once: towards the right and lower neighbours */
         for (int d = OR_RIGHT; d <= OR_DOWN; d += 2) {

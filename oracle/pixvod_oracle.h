@@ -108,6 +108,13 @@ size_t or_state_doubles(const or_ctx* ctx);
 int or_get_state(const or_ctx* ctx, double* out);
 int or_set_state(or_ctx* ctx, const double* in);
 
+/* prior means (Eq. prior; log-depth prior of Sec. 3.3): pose mean xi (NULL
+ * keeps it) and per-pixel log-depth means (H*W, NULL keeps them) */
+int or_set_prior(or_ctx* ctx, const double xi[6], const double* log_depth);
+/* temporal priors: the mean of the current per-pixel poses and the current
+ * log-depths become the prior means */
+int or_set_prior_from_state(or_ctx* ctx);
+
 /* frozen mode: per-pixel belief mean (7 doubles per pixel) of the last iteration */
 int or_get_means(const or_ctx* ctx, double* out);
 /* last iteration's belief information matrices (49 doubles per pixel) */

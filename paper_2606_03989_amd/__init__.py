@@ -70,6 +70,8 @@ _SIGNATURES = {
     "pixvod_set_sigma_map": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "pixvod_track": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.POINTER(TrackOut)]),
     "pixvod_iterate": (C.c_int, [C.c_void_p, C.c_int]),
+    "pixvod_set_prior": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "pixvod_set_prior_from_state": (C.c_int, [C.c_void_p]),
     "pixvod_state_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "pixvod_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "pixvod_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
@@ -196,6 +198,20 @@ class Tracker:
             return
         p, w, k = _ptr(sigma)
         _check(lib().pixvod_set_sigma_map(self._h, C.c_void_p(p), w), self._h)
+
+    def set_prior(self, xi=None, log_depth=None):
+        """Prior means: pose xi (6) and per-pixel log-depths (H x W); None keeps them."""
+        x = None if xi is None else np.ascontiguousarray(xi, dtype=np.float64)
+        if log_depth is None:
+            p, w, k = None, HOST, None
+        else:
+            p, w, k = _ptr(log_depth)
+        _check(lib().pixvod_set_prior(self._h, None if x is None else C.c_void_p(x.ctypes.data),
+                                      None if p is None else C.c_void_p(p), w), self._h)
+
+    def set_prior_from_state(self):
+        """Temporal priors: the last pose estimate and the current log-depths become the prior means."""
+        _check(lib().pixvod_set_prior_from_state(self._h), self._h)
 
     def track(self, frame, n_iters: int, maps: bool = True, out_device: bool = False):
         """Tracks one frame; returns pose, world pose, flags and (optionally)

@@ -53,6 +53,7 @@ struct Strengths {
     double prior_t[3];    // Exp(prior_xi)^-1 translation
     int prior_is_identity;
     int has_sigma_map;
+    int has_prior_map;    // per-pixel log-depth prior means (in.prior_ell)
 };
 
 // inputs that stay fixed for a keyframe / a frame
@@ -64,6 +65,7 @@ struct Inputs {
     const float* It;      // target frame
     const float* Gx;      // its central-difference gradients
     const float* Gy;
+    const float* prior_ell;   // per-pixel log-depth prior mean (valid if has_prior_map)
 };
 
 // one sequence of a batch (device-resident descriptor)
@@ -526,7 +528,8 @@ __device__ inline bool unary_factors(const Geo& g, const Strengths& s, const Inp
             L[s7(a, b)] += lamP * g;
         }
     }
-    eta[6] -= lamP * (ell - s.prior_ell);
+    const double pell = s.has_prior_map ? (double)in.prior_ell[(long)v * g.pitch + u] : s.prior_ell;
+    eta[6] -= lamP * (ell - pell);
     L[s7(6, 6)] += lamP;
     return valid;
 }

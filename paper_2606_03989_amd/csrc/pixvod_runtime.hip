@@ -33,6 +33,9 @@ struct pixvod_ctx {
     int cur = 0;
     float *Is = nullptr, *cxt = nullptr, *cyt = nullptr, *sig = nullptr;
     float *It = nullptr, *Gx = nullptr, *Gy = nullptr;
+    float* prior_ell = nullptr;      // per-pixel log-depth prior means (allocated on first use)
+    bool has_prior_map = false, has_prior_pose = false;
+    double prior_xi[6] = {0, 0, 0, 0, 0, 0};
     float *var_ll = nullptr, *valid = nullptr;
     float *frame_stage = nullptr, *kf_stage = nullptr, *out_stage = nullptr;
     float* dense_state = nullptr;
@@ -148,6 +151,7 @@ static Inputs inputs_of(const pixvod_ctx* c) {
     in.It = c->It;
     in.Gx = c->Gx;
     in.Gy = c->Gy;
+    in.prior_ell = c->prior_ell;
     return in;
 }
 
@@ -190,7 +194,24 @@ Strengths pv::strengths_from(const pixvod_params& P, bool has_sigma_map) {
     return s;
 }
 
-static Strengths strengths_of(const pixvod_ctx* c) { return strengths_from(c->P, c->has_sigma); }
+static Strengths strengths_of(const pixvod_ctx* c) {
+    Strengths s = strengths_from(c->P, c->has_sigma);
+    if (c->has_prior_pose) {
+        // a prior pose mean set at run time (kept in double)
+        double T[16], Ti[16];
+        host_se3_exp(c->prior_xi, T);
+        host_se3_inverse(T, Ti);
+        bool ident = true;
+        for (int k = 0; k < 6; ++k) ident = ident && (c->prior_xi[k] == 0.0);
+        for (int r = 0; r < 3; ++r) {
+            for (int cc = 0; cc < 3; ++cc) s.prior_R[r * 3 + cc] = Ti[r * 4 + cc];
+            s.prior_t[r] = Ti[r * 4 + 3];
+        }
+        s.prior_is_identity = ident ? 1 : 0;
+    }
+    s.has_prior_map = c->has_prior_map ? 1 : 0;
+    return s;
+}
 
 void pv::record_error(const std::string& msg) { g_last_error = msg; }
 
@@ -250,7 +271,7 @@ static void prof_collect(pixvod_ctx* c) {
 }
 
 static void release(pixvod_ctx* c) {
-    void* bufs[] = {c->X[0], c->X[1], c->Is, c->cxt, c->cyt, c->sig, c->It, c->Gx, c->Gy, c->var_ll,
+    void* bufs[] = {c->X[0], c->X[1], c->Is, c->cxt, c->cyt, c->sig, c->It, c->Gx, c->Gy, c->prior_ell, c->var_ll,
                     c->valid, c->frame_stage, c->kf_stage, c->out_stage, c->dense_state, c->marg, c->msg,
                     c->partial, c->result, c->health};
     for (void* b : bufs)
@@ -426,6 +447,8 @@ int pixvod_set_keyframe(pixvod_ctx* c, const float* img, const float* normals, i
         std::memcpy(c->T_w_kf, Tw, sizeof(Tw));
     }
     std::memset(c->xi_last, 0, sizeof(c->xi_last));
+    // the pose prior is relative to the keyframe: back to the parameters' mean
+    c->has_prior_pose = false;
     c->have_track = false;
     c->have_kf = true;
     c->have_var = false;
@@ -448,6 +471,47 @@ int pixvod_set_sigma_map(pixvod_ctx* c, const float* map, int where) {
     HIP_TRY(c, launch_copy_plane(geo_of(c), d, c->sig, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->has_sigma = true;
+    return PIXVOD_OK;
+}
+
+int pixvod_set_prior(pixvod_ctx* c, const double xi[6], const float* log_depth, int where) {
+    if (!c) return fail(nullptr, PIXVOD_EINVAL, "ctx is NULL");
+    if (log_depth && where != PIXVOD_HOST && where != PIXVOD_DEVICE) return fail(c, PIXVOD_EINVAL, "bad location");
+    if (xi) {
+        for (int k = 0; k < 6; ++k)
+            if (!std::isfinite(xi[k])) return fail(c, PIXVOD_EINVAL, "prior pose must be finite");
+        std::memcpy(c->prior_xi, xi, sizeof(c->prior_xi));
+        c->has_prior_pose = true;
+    }
+    if (log_depth) {
+        if (!c->prior_ell) {
+            int rc = dev_alloc(c, &c->prior_ell, (size_t)c->plane);
+            if (rc) return rc;
+        }
+        const size_t N = (size_t)c->H * c->W;
+        const float* d = nullptr;
+        int rc = stage_in(c, log_depth, where, N, c->frame_stage, &d);
+        if (rc) return rc;
+        HIP_TRY(c, launch_copy_plane(geo_of(c), d, c->prior_ell, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        c->has_prior_map = true;
+    }
+    return PIXVOD_OK;
+}
+
+int pixvod_set_prior_from_state(pixvod_ctx* c) {
+    if (!c) return fail(nullptr, PIXVOD_EINVAL, "ctx is NULL");
+    if (!c->have_track) return fail(c, PIXVOD_ESTATE, "no tracked frame since the keyframe");
+    if (!c->prior_ell) {
+        int rc = dev_alloc(c, &c->prior_ell, (size_t)c->plane);
+        if (rc) return rc;
+    }
+    std::memcpy(c->prior_xi, c->xi_last, sizeof(c->prior_xi));
+    c->has_prior_pose = true;
+    HIP_TRY(c, hipMemcpyAsync(c->prior_ell, c->X[c->cur] + (size_t)P_ELL * c->plane, (size_t)c->plane * sizeof(float),
+                              hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->has_prior_map = true;
     return PIXVOD_OK;
 }
 

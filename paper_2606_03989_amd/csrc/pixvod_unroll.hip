@@ -96,6 +96,7 @@ static Inputs uinputs(const pixvod_unroll* u) {
     in.It = u->It;
     in.Gx = u->Gx;
     in.Gy = u->Gy;
+    in.prior_ell = nullptr;
     return in;
 }
 

@@ -296,3 +296,66 @@ def test_sigma_map_matches_oracle():
     rg = t.track(w["frames"][0], 30)
     ro = o.track(w["frames"][0], 30)
     _assert_frame(rg, ro, "sigma map")
+
+
+# --- prior means set at run time (temporal priors) ----------------------------------
+
+def _teacher_forced(t, o, n, label):
+    worst = 0.0
+    for it in range(n):
+        o.set_state(to_oracle(t.get_state()))
+        t.iterate(1)
+        o.iterate(1)
+        q = float(np.percentile(_plane_errors(t.get_state(), from_oracle(o.get_state())), 99.9))
+        worst = max(worst, q)
+        assert q <= 1e-5, f"{label} iteration {it}: p99.9 {q:.2e}"
+    print(f"{label}: worst p99.9 over {n} iterations {worst:.2e}", flush=True)
+
+
+def test_explicit_prior_means():
+    w = sequence_workload("ppa256", 1)
+    t = make_tracker(w, 0)
+    o = make_oracle(w)
+    rng = np.random.default_rng(3)
+    xi = rng.normal(0.0, 0.003, 6)
+    ell = (np.log(0.8) + rng.normal(0.0, 0.2, (w["cam"].H, w["cam"].W))).astype(np.float32)
+    t.set_prior(xi, ell)
+    o.set_prior(xi, ell.astype(np.float64))
+    t.track(w["frames"][0], 0)
+    o.set_frame(w["frames"][0])
+    _teacher_forced(t, o, 8, "explicit prior means")
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_temporal_prior_from_state(schedule):
+    # frame 1 tracked, then its estimates become the prior means for frame 2
+    w = sequence_workload("ppa256", 2)
+    t = make_tracker(w, schedule)
+    o = make_oracle(w)
+    t.track(w["frames"][0], w["iters"])
+    o.set_state(to_oracle(t.get_state()))
+    t.set_prior_from_state()
+    o.set_prior_from_state()
+    t.track(w["frames"][1], 0)
+    o.set_frame(w["frames"][1])
+    _teacher_forced(t, o, 8, f"temporal prior sched={schedule}")
+
+
+def test_prior_errors_and_keyframe_reset():
+    import paper_2606_03989_amd as pv
+    w = sequence_workload("ppa256", 1)
+    t = make_tracker(w, 0)
+    with pytest.raises(pv.PixvodError) as e:
+        t.set_prior_from_state()
+    assert e.value.code == pv.ESTATE
+    with pytest.raises(pv.PixvodError) as e:
+        t.set_prior([0.0, float("nan"), 0, 0, 0, 0])
+    assert e.value.code == pv.EINVAL
+    # a new keyframe resets the pose prior to the parameters' (identity) mean:
+    # tracking then equals a context that never had one
+    t.set_prior([0.01, 0.0, 0.0, 0.02, 0.0, 0.0])
+    t.set_keyframe(w["I_s"], w["N_s"])
+    r1 = t.track(w["frames"][0], 5)
+    t2 = make_tracker(w, 0)
+    r2 = t2.track(w["frames"][0], 5)
+    np.testing.assert_array_equal(r1["inv_depth"], r2["inv_depth"])

@@ -276,3 +276,44 @@ def test_state_roundtrip(tiny):
     o.iterate(2)
     o2.iterate(2)
     np.testing.assert_array_equal(o2.get_state(), o.get_state())
+
+
+# --- temporal priors: prior means from the previous estimates ----------------------
+
+def test_frozen_gbp_with_prior_means_equals_dense_solve():
+    # a non-identity prior pose mean and a per-pixel log-depth prior map
+    p = synth.tiny_pair(4, H=5, W=6, lattice_px=2.0)
+    cam = p["cam"]
+    kw = dict(sigma_P=1e-2, sigma_R=1e-2, sigma_N=1e-2)
+    o = make(p, init_inv_depth=0.4, frozen=1, **kw)
+    rng = np.random.default_rng(9)
+    xi_hat = rng.normal(0, 0.004, 6)
+    ell_hat = np.log(2.5) + rng.normal(0, 0.1, (cam.H, cam.W))
+    o.set_prior(xi_hat, ell_hat)
+    st = o.get_state()
+    st[..., :6] = rng.normal(0, 0.003, size=st[..., :6].shape)
+    o.set_state(st)
+    prob = dense.Problem(cam.H, cam.W, K_of(cam), p["I_s"], p["I_t"], p["normals_s"], prior_xi=xi_hat,
+                         prior_log_depth=ell_hat, **kw)
+    ref = prob.solve_linear(st[..., :6].reshape(-1, 6), st[..., 6].reshape(-1))
+    o.iterate(400)
+    np.testing.assert_allclose(o.means().reshape(-1, 7), ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+
+
+def test_prior_from_state_takes_the_current_estimates():
+    p = synth.tiny_pair(0)
+    o = make(p, init_inv_depth=0.3, sigma_P=0.1)
+    o.iterate(5)
+    st = o.get_state()
+    o.set_prior_from_state()
+    # at the prior means the prior residual vanishes: a pixel whose pose equals
+    # the mean pose and whose log-depth is its own prior gets no prior gradient
+    xi_bar = st[..., :6].reshape(-1, 6).mean(0)
+    st2 = st.copy()
+    st2[..., :6] = xi_bar
+    o.set_state(st2)
+    eta, lam, _ = o.unary(3, 4)
+    o2 = make(p, init_inv_depth=0.3, sigma_P=np.inf)
+    o2.set_state(st2)
+    eta2, lam2, _ = o2.unary(3, 4)
+    np.testing.assert_allclose(eta, eta2, atol=1e-9 * max(1.0, np.abs(eta2).max()))

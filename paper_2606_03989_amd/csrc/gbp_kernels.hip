@@ -766,6 +766,10 @@ hipError_t launch_batch_passes(const BatchLaunch& b, int n_iters, bool prologue,
 
 static dim3 grid2d(const Geo& g, dim3 b) { return dim3((g.W + b.x - 1) / b.x, (g.H + b.y - 1) / b.y); }
 static const dim3 kBlock(64, 1);
+// fused passes: 64 x 4 tiles keep the vertical neighbours' points and partials
+// in the same workgroup's cache lines (measured 1.15x against 1.24x of the
+// algorithmic bytes for 64 x 1 at 640x480, same duration)
+static const dim3 kBlockFused(64, 4);
 
 hipError_t launch_frame_prep(const Geo& g, const float* src, long src_pitch, float* It, float* Gx, float* Gy,
                              hipStream_t st) {
@@ -794,24 +798,24 @@ hipError_t launch_pf_iteration(const Geo& g, const Strengths& s, const Inputs& i
 
 hipError_t launch_fu_prologue(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* Y,
                               int* health, hipStream_t st) {
-    hipLaunchKernelGGL(k_fu_prologue, grid2d(g, kBlock), kBlock, 0, st, g, s, in, X, Y, health);
+    hipLaunchKernelGGL(k_fu_prologue, grid2d(g, kBlockFused), kBlockFused, 0, st, g, s, in, X, Y, health);
     return hipGetLastError();
 }
 
 hipError_t launch_fu_iterate(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* Y,
                              bool final_pass, float* var_ll, float* valid, int* health, hipStream_t st) {
     if (final_pass)
-        hipLaunchKernelGGL(k_fu_iterate<true>, grid2d(g, kBlock), kBlock, 0, st, g, s, in, X, Y, var_ll, valid, health);
+        hipLaunchKernelGGL(k_fu_iterate<true>, grid2d(g, kBlockFused), kBlockFused, 0, st, g, s, in, X, Y, var_ll, valid, health);
     else
-        hipLaunchKernelGGL(k_fu_iterate<false>, grid2d(g, kBlock), kBlock, 0, st, g, s, in, X, Y, var_ll, valid, health);
+        hipLaunchKernelGGL(k_fu_iterate<false>, grid2d(g, kBlockFused), kBlockFused, 0, st, g, s, in, X, Y, var_ll, valid, health);
     return hipGetLastError();
 }
 
 hipError_t launch_fu_step_tape(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* tmp,
                                float* Y, double* marg, double* M, double* bel, float* var_ll, float* valid,
                                int* health, hipStream_t st) {
-    hipLaunchKernelGGL(k_fu_prologue_tape, grid2d(g, kBlock), kBlock, 0, st, g, s, in, X, tmp, marg, health);
-    hipLaunchKernelGGL(k_fu_final_tape, grid2d(g, kBlock), kBlock, 0, st, g, s, in, tmp, Y, M, bel, var_ll, valid,
+    hipLaunchKernelGGL(k_fu_prologue_tape, grid2d(g, kBlockFused), kBlockFused, 0, st, g, s, in, X, tmp, marg, health);
+    hipLaunchKernelGGL(k_fu_final_tape, grid2d(g, kBlockFused), kBlockFused, 0, st, g, s, in, tmp, Y, M, bel, var_ll, valid,
                        health);
     return hipGetLastError();
 }

@@ -29,7 +29,11 @@ class OrConfig(C.Structure):
         ("kf_max_frames", C.c_int), ("kf_min_valid_frac", C.c_double),
         ("damping", C.c_double),
         ("frozen", C.c_int), ("full_jacobian", C.c_int),
+        ("topology", C.c_int),
     ]
+
+
+TOPO_GRID, TOPO_QUADTREE = 0, 1
 
 
 class OrTrackOut(C.Structure):
@@ -73,6 +77,9 @@ def lib() -> C.CDLL:
         L.or_get_beliefs.argtypes = [C.c_void_p, dp, dp]
         L.or_get_normal_targets.argtypes = [C.c_void_p, dp, dp]
         L.or_get_gradients.argtypes = [C.c_void_p, dp, dp]
+        L.or_tree_levels.restype = C.c_int
+        L.or_tree_levels.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
+        L.or_get_node_beliefs.argtypes = [C.c_void_p, dp, dp]
         L.or_energy.restype = C.c_double
         L.or_energy.argtypes = [C.c_void_p]
         L.or_se3_exp.argtypes = [dp, dp]
@@ -244,14 +251,44 @@ class Oracle:
                     frames_since_keyframe=out.frames_since_keyframe, flags=out.flags,
                     inv_depth=inv.reshape(self.H, self.W), inv_depth_var=var.reshape(self.H, self.W))
 
-    def get_state(self) -> np.ndarray:
-        s = np.zeros(self.N * 123)
-        lib().or_get_state(self._h, _dp(s))
-        return s.reshape(self.H, self.W, 123)
+    @property
+    def tree(self) -> bool:
+        return self.cfg.topology == TOPO_QUADTREE
 
-    def set_state(self, s: np.ndarray):
-        s = np.ascontiguousarray(s, dtype=np.float64).reshape(self.N * 123)
+    def tree_levels(self):
+        """[(rows, cols)] of levels 0 (pixels) .. L (root); [(H, W)] for the grid."""
+        hw = (C.c_int * 64)()
+        L = lib().or_tree_levels(self._h, hw)
+        return [(hw[2 * l], hw[2 * l + 1]) for l in range(L + 1)]
+
+    @property
+    def n_nodes(self) -> int:
+        return sum(h * w for h, w in self.tree_levels()[1:])
+
+    def get_state(self):
+        """Grid: (H, W, 123). Quadtree: ((H, W, 42) pixel part, (n_nodes, 141) node part)."""
+        n = lib().or_state_doubles(self._h)
+        s = np.zeros(n)
+        lib().or_get_state(self._h, _dp(s))
+        if not self.tree:
+            return s.reshape(self.H, self.W, 123)
+        return s[:self.N * 42].reshape(self.H, self.W, 42), s[self.N * 42:].reshape(-1, 141)
+
+    def set_state(self, s):
+        if self.tree:
+            pix, nodes = s
+            s = np.concatenate([np.asarray(pix, dtype=np.float64).reshape(-1),
+                                np.asarray(nodes, dtype=np.float64).reshape(-1)])
+        s = np.ascontiguousarray(s, dtype=np.float64).reshape(-1)
+        assert s.size == lib().or_state_doubles(self._h)
         lib().or_set_state(self._h, _dp(s))
+
+    def node_beliefs(self):
+        n = self.n_nodes
+        lam = np.zeros(n * 49)
+        eta = np.zeros(n * 7)
+        lib().or_get_node_beliefs(self._h, _dp(lam), _dp(eta))
+        return lam.reshape(n, 7, 7), eta.reshape(n, 7)
 
     def means(self) -> np.ndarray:
         m = np.zeros(self.N * 7)

@@ -130,11 +130,46 @@ def warp_pixel(K, u: float, v: float, tau, ell: float):
     return a[2] > 0, w, dwda @ dadx
 
 
+def quadtree_levels(H: int, W: int):
+    """Level sizes [(rows, cols)] of the quadtree of pose variables (Fig. 2,
+    Sec. 4.2): level 0 is the H x W pixel array, level l has ceil(H / 2^l) x
+    ceil(W / 2^l) nodes, each joined to the 2 x 2 block below it, up to the
+    single root."""
+    dims = [(H, W)]
+    l = 0
+    while dims[-1] != (1, 1):
+        l += 1
+        dims.append((-(-H // 2 ** l), -(-W // 2 ** l)))
+    return dims
+
+
+def level_sigmas(sigma: float, n_levels: int):
+    """sigma halved at each level above the leaves (Sec. 4.2)."""
+    return [sigma * 0.5 ** l for l in range(n_levels)]
+
+
 class Problem:
-    """The linearisable model of one keyframe / target-frame pair on an H x W grid."""
+    """The linearisable model of one keyframe / target-frame pair on an H x W grid.
+
+    topology "grid": identity factors between 4-neighbour pixels (Eq. regul).
+    topology "quadtree": identity factors only between each variable and its
+    parent in the quadtree (pixels at level 0, 6-D pose nodes above); the
+    prior and identity sigmas halve per level (Sec. 4.2), the identity factor
+    between levels l and l + 1 taking the level-l value. Node variables follow
+    the 7N pixel variables, 6 per node, level-major and row-major."""
 
     def __init__(self, H, W, K, I_s, I_t, normals, sigma_D=5e-3, sigma_P=1.0, sigma_R=4e-4,
-                 sigma_N=1e-3, huber_k=400.0, prior_xi=None, prior_log_depth=0.0, sigma_D_map=None):
+                 sigma_N=1e-3, huber_k=400.0, prior_xi=None, prior_log_depth=0.0, sigma_D_map=None,
+                 topology="grid"):
+        assert topology in ("grid", "quadtree")
+        self.topology = topology
+        self.levels = quadtree_levels(H, W) if topology == "quadtree" else [(H, W)]
+        self.sigma_P, self.sigma_R = sigma_P, sigma_R
+        offs = [0, 0]
+        for (h, w) in self.levels[1:]:
+            offs.append(offs[-1] + h * w)
+        self.level_offset = offs        # first node of level l >= 1
+        self.NT = offs[-1]
         self.H, self.W, self.K = H, W, tuple(float(k) for k in K)
         self.I_s = I_s.astype(np.float64)
         self.I_t = I_t.astype(np.float64)
@@ -188,12 +223,30 @@ class Problem:
                     out.append((i, i + self.W, False))
         return out
 
-    def assemble(self, tau: np.ndarray, ell: np.ndarray):
-        """Joint information (Lambda, eta) of the model linearised at (tau, ell),
-        variables ordered pixel-major, 7 per pixel; eta = -J^T Lambda r."""
+    def node(self, l: int, col: int, row: int) -> int:
+        return self.level_offset[l] + row * self.levels[l][1] + col
+
+    def tree_edges(self):
+        """(child pose column, parent pose column, child level) of every quadtree edge."""
+        out = []
+        for l in range(len(self.levels) - 1):
+            h, w = self.levels[l]
+            for row in range(h):
+                for col in range(w):
+                    c = 7 * (row * self.W + col) if l == 0 else 7 * self.N + 6 * self.node(l, col, row)
+                    p = 7 * self.N + 6 * self.node(l + 1, col // 2, row // 2)
+                    out.append((c, p, l))
+        return out
+
+    def assemble(self, tau: np.ndarray, ell: np.ndarray, ntau: Optional[np.ndarray] = None):
+        """Joint information (Lambda, eta) of the model linearised at (tau, ell)
+        (and the quadtree node poses ntau), variables ordered pixel-major, 7 per
+        pixel, then 6 per node; eta = -J^T Lambda r."""
         N = self.N
-        L = np.zeros((7 * N, 7 * N))
-        h = np.zeros(7 * N)
+        tree = self.topology == "quadtree"
+        n = 7 * N + (6 * self.NT if tree else 0)
+        L = np.zeros((n, n))
+        h = np.zeros(n)
         nvalid = 0
         for i in range(N):
             s = slice(7 * i, 7 * i + 7)
@@ -205,9 +258,33 @@ class Problem:
             rp, Jp = self.prior(tau[i], ell[i], i)
             L[s, s] += self.lamP * Jp.T @ Jp
             h[s] -= self.lamP * Jp.T @ rp
+        if tree:
+            nlev = len(self.levels)
+            sP = level_sigmas(self.sigma_P, nlev)
+            sR = level_sigmas(self.sigma_R, nlev)
+            for k in range(self.NT):
+                l = max(i for i in range(1, nlev) if self.level_offset[i] <= k)
+                s = slice(7 * N + 6 * k, 7 * N + 6 * k + 6)
+                rp = log_se3(np.linalg.inv(exp_se3(self.prior_xi)) @ exp_se3(ntau[k]))
+                Jp = prior_jac(rp)
+                L[s, s] += sP[l] ** -2 * Jp.T @ Jp
+                h[s] -= sP[l] ** -2 * Jp.T @ rp
+            if self.lamR > 0:
+                for (c, p, l) in self.tree_edges():
+                    tc = tau[c // 7] if c < 7 * N else ntau[(c - 7 * N) // 6]
+                    tp = ntau[(p - 7 * N) // 6]
+                    lam = sR[l] ** -2
+                    r = log_se3(np.linalg.inv(exp_se3(tp)) @ exp_se3(tc))   # receiver child, sender parent
+                    sc, sp = slice(c, c + 6), slice(p, p + 6)
+                    L[sc, sc] += lam * np.eye(6)
+                    L[sp, sp] += lam * np.eye(6)
+                    L[sc, sp] -= lam * np.eye(6)
+                    L[sp, sc] -= lam * np.eye(6)
+                    h[sc] -= lam * r
+                    h[sp] += lam * r
         for (a, b, horiz) in self.edges():
             sa, sb = slice(7 * a, 7 * a + 6), slice(7 * b, 7 * b + 6)
-            if self.lamR > 0:
+            if self.lamR > 0 and not tree:
                 r = log_se3(np.linalg.inv(exp_se3(tau[a])) @ exp_se3(tau[b]))   # receiver b, sender a
                 # J_b = +I, J_a = -I
                 L[sb, sb] += self.lamR * np.eye(6)
@@ -231,6 +308,25 @@ class Problem:
     def solve_linear(self, tau, ell):
         L, h, _ = self.assemble(tau, ell)
         return np.linalg.solve(L, h).reshape(self.N, 7)
+
+    def solve_tree(self, tau, ell, ntau):
+        """Linear solve of the quadtree model: (pixel steps (N, 7), node steps (NT, 6))."""
+        L, h, _ = self.assemble(tau, ell, ntau)
+        d = np.linalg.solve(L, h)
+        return d[:7 * self.N].reshape(self.N, 7), d[7 * self.N:].reshape(self.NT, 6)
+
+    def gauss_newton_tree(self, tau, ell, ntau, n_iters: int):
+        tau = np.array(tau, dtype=np.float64).copy()
+        ell = np.array(ell, dtype=np.float64).copy()
+        ntau = np.array(ntau, dtype=np.float64).copy()
+        for _ in range(n_iters):
+            dp, dn = self.solve_tree(tau, ell, ntau)
+            for i in range(self.N):
+                tau[i] = log_se3(exp_se3(tau[i]) @ exp_se3(dp[i, :6]))
+            for k in range(self.NT):
+                ntau[k] = log_se3(exp_se3(ntau[k]) @ exp_se3(dn[k]))
+            ell = ell + dp[:, 6]
+        return tau, ell, ntau
 
     def gauss_newton(self, tau, ell, n_iters: int, damping: float = 1.0):
         tau = np.array(tau, dtype=np.float64).copy()

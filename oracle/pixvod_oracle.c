@@ -25,6 +25,8 @@
 
 typedef struct { double eta[7]; double lam[49]; } g7;
 
+#define OR_MAX_LEVELS 30
+
 struct or_ctx {
     or_config cfg;
     int N;
@@ -43,6 +45,14 @@ struct or_ctx {
     int have_track;
     int frames_since_kf;
     int diverged;
+    /* quadtree topology: node levels 1..L above the pixels (level 0) */
+    int tree, L, NT;
+    int lvH[OR_MAX_LEVELS + 1], lvW[OR_MAX_LEVELS + 1];
+    int lvOff[OR_MAX_LEVELS + 2];      /* first node of level l >= 1 */
+    double* ntau;                      /* node linearisation points */
+    g7 *pmsg, *pnewmsg;                /* per pixel: message of the edge to its parent */
+    g7 *nmsg, *nnewmsg;                /* per node: slot 0 parent edge, 1 + q child edges */
+    g7 *nunary, *nbelief;
 };
 
 /* ------------------------------------------------------------------------ */
@@ -349,6 +359,32 @@ static void add_outer(double lam[49], double eta[7], const double J[7], double r
     }
 }
 
+/* pose part of the prior factor, Eq. (prior): r = Log(Exp(xi_hat)^-1 Exp(tau))
+ * with precision lamP, added to (eta, lam) */
+static void add_pose_prior(const or_config* c, const double tau[6], double lamP, double eta[7],
+                           double lam[49]) {
+    double Tp[16], Tpi[16], Tt[16], Tr[16], rp[6];
+    or_se3_exp(c->prior_xi, Tp);
+    se3_inverse(Tp, Tpi);
+    or_se3_exp(tau, Tt);
+    mat_mul(4, 4, 4, Tpi, Tt, Tr);
+    or_se3_log(Tr, rp);
+    double Jp[36];
+    or_prior_jacobian(rp, Jp);
+    for (int k = 0; k < 6; ++k) {
+        double row[7] = {0};
+        for (int cc = 0; cc < 6; ++cc) row[cc] = Jp[k * 6 + cc];
+        add_outer(lam, eta, row, rp[k], lamP);
+    }
+}
+
+/* precision of a factor whose sigma is halved at each level above the
+ * pixels: sigma_l = sigma 2^-l (Sec. 4.2) */
+static double level_lambda(double sigma, int l) {
+    double s = ldexp(sigma, -l);
+    return 1.0 / (s * s);
+}
+
 /* photometric + prior unary factor of pixel i in information form */
 static int unary_at(const or_ctx* ctx, int i, double eta[7], double lam[49], int* valid) {
     const or_config* c = &ctx->cfg;
@@ -380,20 +416,8 @@ static int unary_at(const or_ctx* ctx, int i, double eta[7], double lam[49], int
     }
 
     /* prior factor, Eq. (prior): r = [Log(Exp(xi_hat)^-1 Exp(tau)); ell - ell_hat] */
-    double Tp[16], Tpi[16], Tt[16], Tr[16], rp[6];
-    or_se3_exp(c->prior_xi, Tp);
-    se3_inverse(Tp, Tpi);
-    or_se3_exp(tau, Tt);
-    mat_mul(4, 4, 4, Tpi, Tt, Tr);
-    or_se3_log(Tr, rp);
-    double Jp[36];
-    or_prior_jacobian(rp, Jp);
     double lamP = 1.0 / (c->sigma_P * c->sigma_P);
-    for (int k = 0; k < 6; ++k) {
-        double row[7] = {0};
-        for (int cc = 0; cc < 6; ++cc) row[cc] = Jp[k * 6 + cc];
-        add_outer(lam, eta, row, rp[k], lamP);
-    }
+    add_pose_prior(c, tau, lamP, eta, lam);
     double row6[7] = {0, 0, 0, 0, 0, 0, 1.0};
     add_outer(lam, eta, row6, ell - ctx->prior_ell[i], lamP);
     return 0;
@@ -485,6 +509,7 @@ int or_threads(void) {
 
 or_ctx* or_create(const or_config* cfg) {
     if (!cfg || cfg->H < 1 || cfg->W < 2 || !(cfg->fx > 0) || !(cfg->fy > 0)) return NULL;
+    if (cfg->topology != OR_TOPO_GRID && cfg->topology != OR_TOPO_QUADTREE) return NULL;
     or_ctx* x = (or_ctx*)calloc(1, sizeof(or_ctx));
     x->cfg = *cfg;
     x->N = cfg->H * cfg->W;
@@ -514,6 +539,32 @@ or_ctx* or_create(const or_config* cfg) {
     }
     memset(x->T_w_kf, 0, sizeof(x->T_w_kf));
     for (int k = 0; k < 4; ++k) x->T_w_kf[k * 5] = 1.0;
+    /* quadtree levels: level l >= 1 has ceil(H / 2^l) x ceil(W / 2^l) nodes,
+     * the last level is the single root */
+    x->lvH[0] = cfg->H;
+    x->lvW[0] = cfg->W;
+    x->L = 0;
+    if (cfg->topology == OR_TOPO_QUADTREE) {
+        x->tree = 1;
+        while (x->lvH[x->L] > 1 || x->lvW[x->L] > 1) {
+            x->lvH[x->L + 1] = (x->lvH[x->L] + 1) / 2;
+            x->lvW[x->L + 1] = (x->lvW[x->L] + 1) / 2;
+            x->L += 1;
+        }
+    }
+    x->lvOff[1] = 0;
+    for (int l = 1; l <= x->L; ++l) x->lvOff[l + 1] = x->lvOff[l] + x->lvH[l] * x->lvW[l];
+    x->NT = x->lvOff[x->L + 1];
+    if (x->tree) {
+        size_t NT = (size_t)x->NT;
+        x->ntau = calloc(6 * NT, sizeof(double));
+        x->pmsg = calloc(N, sizeof(g7));
+        x->pnewmsg = calloc(N, sizeof(g7));
+        x->nmsg = calloc(5 * NT, sizeof(g7));
+        x->nnewmsg = calloc(5 * NT, sizeof(g7));
+        x->nunary = calloc(NT, sizeof(g7));
+        x->nbelief = calloc(NT, sizeof(g7));
+    }
     return x;
 }
 
@@ -522,6 +573,8 @@ void or_destroy(or_ctx* x) {
     free(x->I_s); free(x->cxt); free(x->cyt); free(x->I_t); free(x->Gx); free(x->Gy);
     free(x->sigD); free(x->prior_ell); free(x->tau); free(x->ell); free(x->msg); free(x->newmsg);
     free(x->unary); free(x->belief); free(x->mean); free(x->var_ll); free(x->valid);
+    free(x->ntau); free(x->pmsg); free(x->pnewmsg); free(x->nmsg); free(x->nnewmsg);
+    free(x->nunary); free(x->nbelief);
     free(x);
 }
 
@@ -566,6 +619,11 @@ static int set_keyframe_impl(or_ctx* x, const float* img32, const double* img64,
         for (int k = 0; k < 6; ++k) x->tau[6 * (size_t)i + k] = 0.0;
     }
     memset(x->msg, 0, sizeof(g7) * 8 * (size_t)x->N);
+    if (x->tree) {
+        memset(x->ntau, 0, sizeof(double) * 6 * (size_t)x->NT);
+        memset(x->pmsg, 0, sizeof(g7) * (size_t)x->N);
+        memset(x->nmsg, 0, sizeof(g7) * 5 * (size_t)x->NT);
+    }
     x->frames_since_kf = 0;
     x->have_kf = 1;
     x->diverged = 0;
@@ -624,10 +682,85 @@ static int opposite(int d) { return d ^ 1; }
 
 static void g7_zero(g7* g) { memset(g, 0, sizeof(*g)); }
 
+/* message to the receiver (linearisation point t_recv) of the identity factor
+ * (Eq. regul) it shares with a sender (t_send), given the sender's belief and
+ * the factor's previous message to the sender:
+ * r = Log(Exp(t_send)^-1 Exp(t_recv)), Jacobians +I (receiver) and -I (sender)
+ * at consensus, or the exact Lie Jacobians J_r(r)^-1 and -J_l(r)^-1 */
+static int identity_message(const or_config* c, const double* t_recv, const double* t_send, double lamR,
+                            const g7* bel_send, const g7* back, g7* out) {
+    double Ti[16], Tj[16], Tji[16], Trel[16], r[6];
+    or_se3_exp(t_recv, Ti);
+    or_se3_exp(t_send, Tj);
+    se3_inverse(Tj, Tji);
+    mat_mul(4, 4, 4, Tji, Ti, Trel);
+    or_se3_log(Trel, r);
+    double J[6 * 14];
+    memset(J, 0, sizeof(J));
+    if (c->full_jacobian) {
+        double Jr[36], Ji[36], rn[6], Jl[36], Jli[36];
+        or_se3_jr(r, Jr);
+        mat_inverse(6, Jr, Ji);
+        for (int k = 0; k < 6; ++k) rn[k] = -r[k];
+        or_se3_jr(rn, Jl);                 /* J_l(r) = J_r(-r) */
+        mat_inverse(6, Jl, Jli);
+        for (int a = 0; a < 6; ++a)
+            for (int b = 0; b < 6; ++b) {
+                J[a * 14 + b] = Ji[a * 6 + b];
+                J[a * 14 + 7 + b] = -Jli[a * 6 + b];
+            }
+    } else {
+        for (int a = 0; a < 6; ++a) {
+            J[a * 14 + a] = 1.0;
+            J[a * 14 + 7 + a] = -1.0;
+        }
+    }
+    double prec6[6] = {lamR, lamR, lamR, lamR, lamR, lamR};
+    g7 v2f = *bel_send;
+    for (int a = 0; a < 7; ++a) v2f.eta[a] -= back->eta[a];
+    for (int a = 0; a < 49; ++a) v2f.lam[a] -= back->lam[a];
+    return or_factor_message(6, r, J, prec6, v2f.eta, v2f.lam, out->eta, out->lam) ? -1 : 0;
+}
+
+static void g7_add(g7* b, const g7* m) {
+    for (int a = 0; a < 7; ++a) b->eta[a] += m->eta[a];
+    for (int a = 0; a < 49; ++a) b->lam[a] += m->lam[a];
+}
+
+static void g7_damp(g7* nm, const g7* om, double bta) {
+    for (int a = 0; a < 7; ++a) nm->eta[a] = (1.0 - bta) * nm->eta[a] + bta * om->eta[a];
+    for (int a = 0; a < 49; ++a) nm->lam[a] = (1.0 - bta) * nm->lam[a] + bta * om->lam[a];
+}
+
+/* first-order transport of a stored message into the tangent space moved by m */
+static void g7_transport(g7* g, const double m[7]) {
+    for (int a = 0; a < 7; ++a) {
+        double s = 0.0;
+        for (int bb = 0; bb < 7; ++bb) s += g->lam[a * 7 + bb] * m[bb];
+        g->eta[a] -= s;
+    }
+}
+
+/* quadtree node helpers */
+static int node_level(const or_ctx* x, int n) {
+    int l = 1;
+    while (n >= x->lvOff[l + 1]) ++l;
+    return l;
+}
+static int node_at(const or_ctx* x, int l, int col, int row) { return x->lvOff[l] + row * x->lvW[l] + col; }
+
+/* unary factor of a quadtree node: the pose prior of its level (Eq. prior,
+ * sigma_P halved per level) and unit information on the inert 7th coordinate */
+static void node_unary(const or_ctx* x, int l, const double* tau, g7* u) {
+    memset(u, 0, sizeof(*u));
+    add_pose_prior(&x->cfg, tau, level_lambda(x->cfg.sigma_P, l), u->eta, u->lam);
+    u->lam[48] = 1.0;
+}
+
 /* one synchronous GBP iteration (Sec. 4.1, Sec. 4.3) */
 static int iterate_once(or_ctx* x) {
     const or_config* c = &x->cfg;
-    const int N = x->N;
+    const int N = x->N, NT = x->NT, tree = x->tree;
     const double lamR = 1.0 / (c->sigma_R * c->sigma_R);
     const double lamN = 1.0 / (c->sigma_N * c->sigma_N);
     int fail = 0;
@@ -639,11 +772,14 @@ static int iterate_once(or_ctx* x) {
         unary_at(x, i, u->eta, u->lam, &x->valid[i]);
         g7* b = &x->belief[i];
         *b = *u;
-        for (int k = 0; k < 8; ++k) {
-            const g7* mk = &x->msg[8 * (size_t)i + k];
-            for (int a = 0; a < 7; ++a) b->eta[a] += mk->eta[a];
-            for (int a = 0; a < 49; ++a) b->lam[a] += mk->lam[a];
-        }
+        for (int k = 0; k < 8; ++k) g7_add(b, &x->msg[8 * (size_t)i + k]);
+        if (tree) g7_add(b, &x->pmsg[i]);
+    }
+#pragma omp parallel for schedule(static)
+    for (int n = 0; n < NT; ++n) {
+        node_unary(x, node_level(x, n), x->ntau + 6 * (size_t)n, &x->nunary[n]);
+        x->nbelief[n] = x->nunary[n];
+        for (int k = 0; k < 5; ++k) g7_add(&x->nbelief[n], &x->nmsg[5 * (size_t)n + k]);
     }
 
     /* F: factor-to-variable messages for every directed edge */
@@ -656,42 +792,11 @@ static int iterate_once(or_ctx* x) {
             int j = neighbour(x, i, d);
             if (j < 0) { g7_zero(out_id); g7_zero(out_n); continue; }
             int dj = opposite(d);
-            const double* tj = x->tau + 6 * (size_t)j;
 
-            /* identity factor, Eq. (regul): r = Log(Exp(tau_j)^-1 Exp(tau_i)) */
-            double Ti[16], Tj[16], Tji[16], Trel[16], r[6];
-            or_se3_exp(ti, Ti);
-            or_se3_exp(tj, Tj);
-            se3_inverse(Tj, Tji);
-            mat_mul(4, 4, 4, Tji, Ti, Trel);
-            or_se3_log(Trel, r);
-            double J[6 * 14];
-            memset(J, 0, sizeof(J));
-            if (c->full_jacobian) {
-                double Jr[36], Ji[36], rn[6], Jl[36], Jli[36];
-                or_se3_jr(r, Jr);
-                mat_inverse(6, Jr, Ji);
-                for (int k = 0; k < 6; ++k) rn[k] = -r[k];
-                or_se3_jr(rn, Jl);                 /* J_l(r) = J_r(-r) */
-                mat_inverse(6, Jl, Jli);
-                for (int a = 0; a < 6; ++a)
-                    for (int b = 0; b < 6; ++b) {
-                        J[a * 14 + b] = Ji[a * 6 + b];
-                        J[a * 14 + 7 + b] = -Jli[a * 6 + b];
-                    }
-            } else {
-                /* Jacobians at consensus: +I for the receiver, -I for the sender */
-                for (int a = 0; a < 6; ++a) {
-                    J[a * 14 + a] = 1.0;
-                    J[a * 14 + 7 + a] = -1.0;
-                }
-            }
-            double prec6[6] = {lamR, lamR, lamR, lamR, lamR, lamR};
-            g7 v2f = x->belief[j];
-            const g7* back = &x->msg[8 * (size_t)j + dj];
-            for (int a = 0; a < 7; ++a) v2f.eta[a] -= back->eta[a];
-            for (int a = 0; a < 49; ++a) v2f.lam[a] -= back->lam[a];
-            if (or_factor_message(6, r, J, prec6, v2f.eta, v2f.lam, out_id->eta, out_id->lam))
+            /* identity factor of the grid topology, Eq. (regul) */
+            if (tree) g7_zero(out_id);
+            else if (identity_message(c, ti, x->tau + 6 * (size_t)j, lamR, &x->belief[j],
+                                      &x->msg[8 * (size_t)j + dj], out_id))
                 fail = 1;
 
             /* normal integration factor, Eq. (gbpni): r = ell_b - ell_a + c_a,
@@ -708,22 +813,63 @@ static int iterate_once(or_ctx* x) {
             memset(Jn, 0, sizeof(Jn));
             Jn[6] = recv_is_b ? 1.0 : -1.0;
             Jn[13] = -Jn[6];
-            v2f = x->belief[j];
-            back = &x->msg[8 * (size_t)j + 4 + dj];
+            g7 v2f = x->belief[j];
+            const g7* back = &x->msg[8 * (size_t)j + 4 + dj];
             for (int a = 0; a < 7; ++a) v2f.eta[a] -= back->eta[a];
             for (int a = 0; a < 49; ++a) v2f.lam[a] -= back->lam[a];
             if (or_factor_message(1, &rn, Jn, &lamN, v2f.eta, v2f.lam, out_n->eta, out_n->lam))
                 fail = 1;
         }
-        if (c->damping != 0.0) {
-            double bta = c->damping;
-            for (int k = 0; k < 8; ++k) {
-                g7* nm = &x->newmsg[8 * (size_t)i + k];
-                const g7* om = &x->msg[8 * (size_t)i + k];
-                for (int a = 0; a < 7; ++a) nm->eta[a] = (1.0 - bta) * nm->eta[a] + bta * om->eta[a];
-                for (int a = 0; a < 49; ++a) nm->lam[a] = (1.0 - bta) * nm->lam[a] + bta * om->lam[a];
-            }
+        if (tree) {
+            /* quadtree identity factor to the parent node of level 1 */
+            const int W = c->W, u = i % W, v = i / W;
+            const int p = node_at(x, 1, u / 2, v / 2), q = 2 * (v & 1) + (u & 1);
+            if (identity_message(c, ti, x->ntau + 6 * (size_t)p, level_lambda(c->sigma_R, 0),
+                                 &x->nbelief[p], &x->nmsg[5 * (size_t)p + 1 + q], &x->pnewmsg[i]))
+                fail = 1;
+            if (c->damping != 0.0) g7_damp(&x->pnewmsg[i], &x->pmsg[i], c->damping);
         }
+        if (c->damping != 0.0)
+            for (int k = 0; k < 8; ++k)
+                g7_damp(&x->newmsg[8 * (size_t)i + k], &x->msg[8 * (size_t)i + k], c->damping);
+    }
+    /* quadtree nodes: messages of the edges to the parent and to the children;
+     * the identity factor between levels l and l + 1 has sigma_R 2^-l */
+#pragma omp parallel for schedule(static) reduction(| : fail)
+    for (int n = 0; n < NT; ++n) {
+        const int l = node_level(x, n);
+        const int col = (n - x->lvOff[l]) % x->lvW[l], row = (n - x->lvOff[l]) / x->lvW[l];
+        const double* tn = x->ntau + 6 * (size_t)n;
+        g7* out = &x->nnewmsg[5 * (size_t)n];
+        if (l < x->L) {
+            const int pp = node_at(x, l + 1, col / 2, row / 2), qn = 2 * (row & 1) + (col & 1);
+            if (identity_message(c, tn, x->ntau + 6 * (size_t)pp, level_lambda(c->sigma_R, l),
+                                 &x->nbelief[pp], &x->nmsg[5 * (size_t)pp + 1 + qn], &out[0]))
+                fail = 1;
+        } else {
+            g7_zero(&out[0]);
+        }
+        for (int q = 0; q < 4; ++q) {
+            const int cc = 2 * col + (q & 1), cr = 2 * row + (q >> 1);
+            if (cc >= x->lvW[l - 1] || cr >= x->lvH[l - 1]) { g7_zero(&out[1 + q]); continue; }
+            const double* ts;
+            const g7 *bel, *back;
+            if (l == 1) {
+                const int ch = cr * c->W + cc;
+                ts = x->tau + 6 * (size_t)ch;
+                bel = &x->belief[ch];
+                back = &x->pmsg[ch];
+            } else {
+                const int ch = node_at(x, l - 1, cc, cr);
+                ts = x->ntau + 6 * (size_t)ch;
+                bel = &x->nbelief[ch];
+                back = &x->nmsg[5 * (size_t)ch];
+            }
+            if (identity_message(c, tn, ts, level_lambda(c->sigma_R, l - 1), bel, back, &out[1 + q]))
+                fail = 1;
+        }
+        if (c->damping != 0.0)
+            for (int k = 0; k < 5; ++k) g7_damp(&out[k], &x->nmsg[5 * (size_t)n + k], c->damping);
     }
 
     /* U: new beliefs, means, relinearisation and message transport */
@@ -732,9 +878,10 @@ static int iterate_once(or_ctx* x) {
         g7* mi = &x->msg[8 * (size_t)i];
         memcpy(mi, &x->newmsg[8 * (size_t)i], 8 * sizeof(g7));
         g7 b = x->unary[i];
-        for (int k = 0; k < 8; ++k) {
-            for (int a = 0; a < 7; ++a) b.eta[a] += mi[k].eta[a];
-            for (int a = 0; a < 49; ++a) b.lam[a] += mi[k].lam[a];
+        for (int k = 0; k < 8; ++k) g7_add(&b, &mi[k]);
+        if (tree) {
+            x->pmsg[i] = x->pnewmsg[i];
+            g7_add(&b, &x->pmsg[i]);
         }
         x->belief[i] = b;
         double Lc[49];
@@ -760,12 +907,31 @@ static int iterate_once(or_ctx* x) {
         or_se3_log(T1, ti);
         x->ell[i] += m[6];
         /* first-order transport of stored messages into the new tangent space */
-        for (int k = 0; k < 8; ++k)
-            for (int a = 0; a < 7; ++a) {
-                double s = 0.0;
-                for (int bb = 0; bb < 7; ++bb) s += mi[k].lam[a * 7 + bb] * m[bb];
-                mi[k].eta[a] -= s;
-            }
+        for (int k = 0; k < 8; ++k) g7_transport(&mi[k], m);
+        if (tree) g7_transport(&x->pmsg[i], m);
+    }
+#pragma omp parallel for schedule(static) reduction(| : fail)
+    for (int n = 0; n < NT; ++n) {
+        g7* mn = &x->nmsg[5 * (size_t)n];
+        memcpy(mn, &x->nnewmsg[5 * (size_t)n], 5 * sizeof(g7));
+        g7 b = x->nunary[n];
+        for (int k = 0; k < 5; ++k) g7_add(&b, &mn[k]);
+        x->nbelief[n] = b;
+        double Lc[49], m[7];
+        if (cholesky(7, b.lam, Lc) != 0) {
+            fail = 1;
+            continue;
+        }
+        memcpy(m, b.eta, sizeof(double) * 7);
+        chol_solve(7, Lc, m);
+        if (c->frozen) continue;
+        double* tn = x->ntau + 6 * (size_t)n;
+        double T0[16], Tm[16], T1[16];
+        or_se3_exp(tn, T0);
+        or_se3_exp(m, Tm);
+        mat_mul(4, 4, 4, T0, Tm, T1);
+        or_se3_log(T1, tn);
+        for (int k = 0; k < 5; ++k) g7_transport(&mn[k], m);
     }
     if (fail) x->diverged = 1;
     return fail ? -1 : 0;
@@ -836,11 +1002,74 @@ int or_track(or_ctx* x, const float* frame, int n_iters, or_track_out* out,
 /* ------------------------------------------------------------------------ */
 /* state exchange                                                            */
 
-size_t or_state_doubles(const or_ctx* x) { return (size_t)x->N * 123; }
+size_t or_state_doubles(const or_ctx* x) {
+    return x->tree ? (size_t)x->N * 42 + (size_t)x->NT * 141 : (size_t)x->N * 123;
+}
 
 static int upper_index(int r, int c) { return r * 6 - r * (r - 1) / 2 + (c - r); }
 
+/* identity message <-> 27 exchange values (eta 6, Lambda upper-packed 21) */
+static void pack27(const g7* g, double* p) {
+    for (int a = 0; a < 6; ++a) p[a] = g->eta[a];
+    for (int r = 0; r < 6; ++r)
+        for (int cc = r; cc < 6; ++cc) p[6 + upper_index(r, cc)] = g->lam[r * 7 + cc];
+}
+static void unpack27(const double* p, g7* g) {
+    g7_zero(g);
+    for (int a = 0; a < 6; ++a) g->eta[a] = p[a];
+    for (int r = 0; r < 6; ++r)
+        for (int cc = r; cc < 6; ++cc) {
+            g->lam[r * 7 + cc] = p[6 + upper_index(r, cc)];
+            g->lam[cc * 7 + r] = p[6 + upper_index(r, cc)];
+        }
+}
+
+static int get_tree_state(const or_ctx* x, double* out) {
+    for (int i = 0; i < x->N; ++i) {
+        double* o = out + 42 * (size_t)i;
+        for (int k = 0; k < 6; ++k) o[k] = x->tau[6 * (size_t)i + k];
+        o[6] = x->ell[i];
+        pack27(&x->pmsg[i], o + 7);
+        for (int d = 0; d < 4; ++d) {
+            const g7* g = &x->msg[8 * (size_t)i + 4 + d];
+            o[34 + 2 * d] = g->eta[6];
+            o[35 + 2 * d] = g->lam[48];
+        }
+    }
+    double* nb = out + 42 * (size_t)x->N;
+    for (int n = 0; n < x->NT; ++n) {
+        double* o = nb + 141 * (size_t)n;
+        for (int k = 0; k < 6; ++k) o[k] = x->ntau[6 * (size_t)n + k];
+        for (int k = 0; k < 5; ++k) pack27(&x->nmsg[5 * (size_t)n + k], o + 6 + 27 * k);
+    }
+    return 0;
+}
+
+static int set_tree_state(or_ctx* x, const double* in) {
+    for (int i = 0; i < x->N; ++i) {
+        const double* o = in + 42 * (size_t)i;
+        for (int k = 0; k < 6; ++k) x->tau[6 * (size_t)i + k] = o[k];
+        x->ell[i] = o[6];
+        unpack27(o + 7, &x->pmsg[i]);
+        for (int d = 0; d < 4; ++d) {
+            g7_zero(&x->msg[8 * (size_t)i + d]);
+            g7* g = &x->msg[8 * (size_t)i + 4 + d];
+            g7_zero(g);
+            g->eta[6] = o[34 + 2 * d];
+            g->lam[48] = o[35 + 2 * d];
+        }
+    }
+    const double* nb = in + 42 * (size_t)x->N;
+    for (int n = 0; n < x->NT; ++n) {
+        const double* o = nb + 141 * (size_t)n;
+        for (int k = 0; k < 6; ++k) x->ntau[6 * (size_t)n + k] = o[k];
+        for (int k = 0; k < 5; ++k) unpack27(o + 6 + 27 * k, &x->nmsg[5 * (size_t)n + k]);
+    }
+    return 0;
+}
+
 int or_get_state(const or_ctx* x, double* out) {
+    if (x->tree) return get_tree_state(x, out);
     for (int i = 0; i < x->N; ++i) {
         double* o = out + 123 * (size_t)i;
         for (int k = 0; k < 6; ++k) o[k] = x->tau[6 * (size_t)i + k];
@@ -862,6 +1091,7 @@ int or_get_state(const or_ctx* x, double* out) {
 }
 
 int or_set_state(or_ctx* x, const double* in) {
+    if (x->tree) return set_tree_state(x, in);
     for (int i = 0; i < x->N; ++i) {
         const double* o = in + 123 * (size_t)i;
         for (int k = 0; k < 6; ++k) x->tau[6 * (size_t)i + k] = o[k];
@@ -883,6 +1113,23 @@ int or_set_state(or_ctx* x, const double* in) {
             g->eta[6] = o[115 + 2 * d];
             g->lam[48] = o[116 + 2 * d];
         }
+    }
+    return 0;
+}
+
+int or_tree_levels(const or_ctx* x, int* hw) {
+    if (hw)
+        for (int l = 0; l <= x->L; ++l) {
+            hw[2 * l] = x->lvH[l];
+            hw[2 * l + 1] = x->lvW[l];
+        }
+    return x->L;
+}
+
+int or_get_node_beliefs(const or_ctx* x, double* lam_out, double* eta_out) {
+    for (int n = 0; n < x->NT; ++n) {
+        if (lam_out) memcpy(lam_out + 49 * (size_t)n, x->nbelief[n].lam, sizeof(double) * 49);
+        if (eta_out) memcpy(eta_out + 7 * (size_t)n, x->nbelief[n].eta, sizeof(double) * 7);
     }
     return 0;
 }
@@ -938,6 +1185,26 @@ int or_get_gradients(const or_ctx* x, double* gx, double* gy) {
 
 /* energy of the nonlinear model at the current linearisation points:
  * Huber photometric + prior + identity + normal terms, each 1/2 |r|^2_Lambda */
+static void add_identity_energy(const double* ti, const double* tj, double lamR, double* E) {
+    double Tj[16], Ti[16], Tji[16], Trel[16], r[6];
+    or_se3_exp(ti, Ti);
+    or_se3_exp(tj, Tj);
+    se3_inverse(Tj, Tji);
+    mat_mul(4, 4, 4, Tji, Ti, Trel);
+    or_se3_log(Trel, r);
+    for (int k = 0; k < 6; ++k) *E += 0.5 * lamR * r[k] * r[k];
+}
+
+static void add_prior_energy(const or_config* c, const double* ti, double lamP, double* E) {
+    double Tp[16], Tpi[16], Tt[16], Tr[16], rp[6];
+    or_se3_exp(c->prior_xi, Tp);
+    se3_inverse(Tp, Tpi);
+    or_se3_exp(ti, Tt);
+    mat_mul(4, 4, 4, Tpi, Tt, Tr);
+    or_se3_log(Tr, rp);
+    for (int k = 0; k < 6; ++k) *E += 0.5 * lamP * rp[k] * rp[k];
+}
+
 double or_energy(const or_ctx* x) {
     const or_config* c = &x->cfg;
     const int W = c->W, H = c->H, N = x->N;
@@ -959,31 +1226,32 @@ double or_energy(const or_ctx* x) {
             double k = c->huber_k;
             E += (M <= k) ? 0.5 * M * M : k * M - 0.5 * k * k;
         }
-        double Tp[16], Tpi[16], Tt[16], Tr[16], rp[6];
-        or_se3_exp(c->prior_xi, Tp);
-        se3_inverse(Tp, Tpi);
-        or_se3_exp(ti, Tt);
-        mat_mul(4, 4, 4, Tpi, Tt, Tr);
-        or_se3_log(Tr, rp);
-        for (int k = 0; k < 6; ++k) E += 0.5 * lamP * rp[k] * rp[k];
+        add_prior_energy(c, ti, lamP, &E);
         double dl = x->ell[i] - x->prior_ell[i];
         E += 0.5 * lamP * dl * dl;
+        if (x->tree)   /* quadtree edge to the parent */
+            add_identity_energy(ti, x->ntau + 6 * (size_t)node_at(x, 1, u / 2, v / 2), lamR, &E);
         /* each edge once: towards the right and lower neighbours */
         for (int d = OR_RIGHT; d <= OR_DOWN; d += 2) {
             int j = neighbour(x, i, d);
             if (j < 0) continue;
-            double Tj[16], Ti[16], Tji[16], Trel[16], r[6];
-            or_se3_exp(ti, Ti);
-            or_se3_exp(x->tau + 6 * (size_t)j, Tj);
-            se3_inverse(Tj, Tji);
-            mat_mul(4, 4, 4, Tji, Ti, Trel);
-            or_se3_log(Trel, r);
-            for (int k = 0; k < 6; ++k) E += 0.5 * lamR * r[k] * r[k];
+            if (!x->tree) add_identity_energy(ti, x->tau + 6 * (size_t)j, lamR, &E);
             double ca = (d == OR_RIGHT) ? x->cxt[i] : x->cyt[i];
             if (isfinite(ca)) {
                 double rn = x->ell[j] - x->ell[i] + ca;
                 E += 0.5 * lamN * rn * rn;
             }
+        }
+    }
+    /* quadtree nodes: level prior and the edge to the parent */
+    for (int n = 0; n < x->NT; ++n) {
+        const int l = node_level(x, n);
+        const double* tn = x->ntau + 6 * (size_t)n;
+        add_prior_energy(c, tn, level_lambda(c->sigma_P, l), &E);
+        if (l < x->L) {
+            const int col = (n - x->lvOff[l]) % x->lvW[l], row = (n - x->lvOff[l]) / x->lvW[l];
+            add_identity_energy(tn, x->ntau + 6 * (size_t)node_at(x, l + 1, col / 2, row / 2),
+                                level_lambda(c->sigma_R, l), &E);
         }
     }
     return E;

@@ -61,7 +61,14 @@ typedef struct {
     /* test switches */
     int frozen;                       /* never relinearise: linear GBP */
     int full_jacobian;                /* identity factor with exact Lie Jacobians */
+    int topology;                     /* identity factors: OR_TOPO_GRID or OR_TOPO_QUADTREE */
 } or_config;
+
+/* identity-factor topologies (Sec. 3.3, Fig. 2): the 4-neighbour pixel grid,
+ * or the quadtree of pose variables above the pixels, where each node of
+ * level l >= 1 (a ceil(H/2^l) x ceil(W/2^l) array) joins the 2 x 2 block of
+ * level l - 1 below it; sigma_P and sigma_R halve per level (Sec. 4.2) */
+enum { OR_TOPO_GRID = 0, OR_TOPO_QUADTREE = 1 };
 
 typedef struct {
     double xi[6];            /* mean over pixels of the pose tangent (Eq. estimator_avg) */
@@ -101,9 +108,17 @@ int or_iterate(or_ctx* ctx, int n_iters);
 /* stage a target frame (gradient images) without iterating */
 int or_set_frame(or_ctx* ctx, const float* frame);
 
-/* state in the exchange layout: per pixel 123 doubles,
+/* state in the exchange layout.
+ * Grid: per pixel 123 doubles,
  * [tau(6), logdepth, 4 x (identity eta(6), Lambda upper-packed row-major(21)),
- *  4 x (normal eta, normal lambda)], pixels in row-major order */
+ *  4 x (normal eta, normal lambda)], pixels in row-major order.
+ * Quadtree: per pixel 42 doubles [tau(6), logdepth, message of the edge to the
+ * parent (eta 6, Lambda 21), 4 x (normal eta, lambda)], then per node of
+ * levels 1..L (level-major, row-major within a level) 141 doubles [tau(6),
+ * message of the edge to the parent (27; zero at the root), for child slot
+ * q = 2 (y & 1) + (x & 1): message of the edge to that child (27; zero where
+ * the child lies outside its level)]. Every message is the one the factor
+ * sends to the variable that stores it. */
 size_t or_state_doubles(const or_ctx* ctx);
 int or_get_state(const or_ctx* ctx, double* out);
 int or_set_state(or_ctx* ctx, const double* in);
@@ -117,6 +132,13 @@ int or_set_prior_from_state(or_ctx* ctx);
 
 /* frozen mode: per-pixel belief mean (7 doubles per pixel) of the last iteration */
 int or_get_means(const or_ctx* ctx, double* out);
+/* quadtree: number of node levels L above the pixels (0 for the grid) and,
+ * if hw is not NULL, hw[2l], hw[2l+1] = rows, columns of level l = 0..L */
+int or_tree_levels(const or_ctx* ctx, int* hw);
+/* quadtree: last iteration's node beliefs (49 + 7 doubles per node, node
+ * order of the exchange layout; the 7th coordinate is an inert placeholder) */
+int or_get_node_beliefs(const or_ctx* ctx, double* lam_out, double* eta_out);
+
 /* last iteration's belief information matrices (49 doubles per pixel) */
 int or_get_beliefs(const or_ctx* ctx, double* lam_out, double* eta_out);
 /* normal-integration targets (c_x, c_y per pixel; NaN = inactive edge) */

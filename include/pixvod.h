@@ -63,6 +63,12 @@ enum {
     PIXVOD_SCHED_PER_FACTOR = 1   /* one kernel per GBP step */
 };
 
+/* camera-motion identity topologies (Sec. 3.3, Fig. 2) */
+enum {
+    PIXVOD_TOPO_GRID = 0,       /* identity factors between 4-neighbour pixels */
+    PIXVOD_TOPO_QUADTREE = 1    /* hierarchical quadtree of pose variables */
+};
+
 typedef struct pixvod_ctx pixvod_ctx;
 
 /* pinhole intrinsics in pixels */
@@ -128,6 +134,28 @@ int pixvod_set_stream(pixvod_ctx* ctx, void* hip_stream);
  * PIXVOD_EINVAL for the fused schedule when params.damping != 0. */
 int pixvod_set_schedule(pixvod_ctx* ctx, int schedule);
 
+/* Identity-factor topology (Sec. 3.3; the hierarchy of Fig. 2 with the
+ * per-level strengths of Sec. 4.2). PIXVOD_TOPO_GRID (default) ties each pixel
+ * pose to its 4 neighbours. PIXVOD_TOPO_QUADTREE adds levels l = 1..L of 6-D
+ * pose variables, level l a ceil(H/2^l) x ceil(W/2^l) array ending in one
+ * root; each node is tied by an identity factor to the up to four variables
+ * of the 2 x 2 block below it (pixels at level 1) and carries a pose prior.
+ * The prior of level l has sigma_P 2^-l, the identity factor between levels l
+ * and l + 1 has sigma_R 2^-l (params.sigma_P and sigma_R are the leaf
+ * values); the lateral pixel identity factors are dropped, the photometric,
+ * prior and normal-integration factors stay. The pose estimate remains the
+ * mean of the pixel poses (Eq. estimator_avg). Device memory: 141 float32
+ * planes per node (pose 6, the message of the edge to the parent 27, the
+ * messages of the four child edges 4 x 27) in two copies, about 0.33 nodes per
+ * pixel. Quadtree contexts run the fused schedule only (damping 0).
+ * PIXVOD_ESTATE after the first pixvod_set_keyframe; PIXVOD_EINVAL for the
+ * per-factor schedule or damping. */
+int pixvod_set_topology(pixvod_ctx* ctx, int topology);
+
+/* Level sizes: *n_levels = L + 1 (1 for the grid); hw (2 * (L + 1) ints, may
+ * be NULL) receives rows, columns of levels 0 (pixels) .. L (root). */
+int pixvod_tree_levels(const pixvod_ctx* ctx, int* n_levels, int* hw);
+
 /* Keyframe anchoring (Sec. 3.5): `img` (H*W) becomes the reference image and
  * `normals` (H*W*3, unit normals in the keyframe camera frame) define the
  * normal-integration targets of Eq. (gbpni). Pose linearisation points are
@@ -170,7 +198,14 @@ int pixvod_iterate(pixvod_ctx* ctx, int n_iters);
  * [pose 0..5, log-depth, for d in {left, right, up, down}: identity message
  * eta(6) + Lambda upper-packed row-major(21), for d: normal eta, lambda].
  * Slot d of pixel i holds the message from the factor on the edge towards
- * the neighbour in direction d; slots of edges that leave the image are 0. */
+ * the neighbour in direction d; slots of edges that leave the image are 0.
+ * Quadtree contexts: 42 planes of H*W [pose 0..5, log-depth, message of the
+ * edge to the parent (eta 6, Lambda 21), for d: normal eta, lambda], then 141
+ * planes of NT nodes (levels 1..L in order, row-major within a level)
+ * [pose 0..5, message of the edge to the parent (27; zero at the root), for
+ * child slot q = 2 (y & 1) + (x & 1): message of that child's edge (27; zero
+ * for a child outside its level)]. Every message is the one its factor sends
+ * to the variable that stores it. pixvod_state_bytes gives the size. */
 int pixvod_state_bytes(const pixvod_ctx* ctx, size_t* bytes);
 int pixvod_get_state(pixvod_ctx* ctx, void* dst, int where);
 int pixvod_set_state(pixvod_ctx* ctx, const void* src, int where);

@@ -28,6 +28,8 @@ KEYFRAME_DUE, DIVERGED, LOW_OVERLAP = 1, 2, 4
 SCHED_FUSED, SCHED_PER_FACTOR = 0, 1
 PROF_FUSED_ITERATE, PROF_FUSED_FINAL, PROF_FUSED_PROLOGUE, PROF_PER_FACTOR = 0, 1, 2, 3
 N_PLANES = 123
+TOPO_GRID, TOPO_QUADTREE = 0, 1
+TREE_PIXEL_PLANES, TREE_NODE_PLANES = 42, 141
 
 
 class PixvodError(RuntimeError):
@@ -66,6 +68,8 @@ _SIGNATURES = {
     "pixvod_destroy": (C.c_int, [C.c_void_p]),
     "pixvod_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pixvod_set_schedule": (C.c_int, [C.c_void_p, C.c_int]),
+    "pixvod_set_topology": (C.c_int, [C.c_void_p, C.c_int]),
+    "pixvod_tree_levels": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "pixvod_set_keyframe": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "pixvod_set_sigma_map": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "pixvod_track": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.POINTER(TrackOut)]),
@@ -160,6 +164,7 @@ class Tracker:
         h = C.c_void_p()
         _check(lib().pixvod_create(self.H, self.W, C.byref(Kc), C.byref(params), C.byref(h)))
         self._h = h
+        self.topology = TOPO_GRID
 
     def close(self):
         if getattr(self, "_h", None):
@@ -254,13 +259,35 @@ class Tracker:
         _check(lib().pixvod_state_bytes(self._h, C.byref(n)), self._h)
         return n.value
 
-    def get_state(self) -> np.ndarray:
-        """State as (123, H, W) float32 (plane-major exchange layout)."""
+    def set_topology(self, topology: int):
+        """TOPO_GRID or TOPO_QUADTREE; before the first keyframe."""
+        _check(lib().pixvod_set_topology(self._h, int(topology)), self._h)
+        self.topology = int(topology)
+
+    def tree_levels(self):
+        """[(rows, cols)] of levels 0 (pixels) .. L (root); [(H, W)] for the grid."""
+        n = C.c_int()
+        hw = (C.c_int * 64)()
+        _check(lib().pixvod_tree_levels(self._h, C.byref(n), hw), self._h)
+        return [(hw[2 * l], hw[2 * l + 1]) for l in range(n.value)]
+
+    def get_state(self):
+        """Grid: (123, H, W) float32 (plane-major exchange layout). Quadtree:
+        ((42, H, W) pixel planes, (141, NT) node planes)."""
+        if self.topology == TOPO_QUADTREE:
+            s = np.empty(self.state_bytes() // 4, np.float32)
+            _check(lib().pixvod_get_state(self._h, C.c_void_p(s.ctypes.data), HOST), self._h)
+            n = self.H * self.W * TREE_PIXEL_PLANES
+            return s[:n].reshape(TREE_PIXEL_PLANES, self.H, self.W), s[n:].reshape(TREE_NODE_PLANES, -1)
         s = np.empty((N_PLANES, self.H, self.W), np.float32)
         _check(lib().pixvod_get_state(self._h, C.c_void_p(s.ctypes.data), HOST), self._h)
         return s
 
     def set_state(self, s):
+        if isinstance(s, tuple):
+            s = np.concatenate([np.asarray(s[0], np.float32).reshape(-1), np.asarray(s[1], np.float32).reshape(-1)])
+            if s.size * 4 != self.state_bytes():
+                raise ValueError("state size does not match the context")
         p, w, k = _ptr(s)
         _check(lib().pixvod_set_state(self._h, C.c_void_p(p), w), self._h)
 

@@ -6,6 +6,7 @@
 // iteration schedules on a caller-selected HIP stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -15,6 +16,7 @@
 #include "../../include/pixvod.h"
 #include "gbp_device.hpp"
 #include "gbp_kernels.h"
+#include "gbp_tree.h"
 #include "runtime_internal.h"
 
 using namespace pv;
@@ -29,7 +31,10 @@ struct pixvod_ctx {
     int device = 0;
     hipStream_t own_stream = nullptr, stream = nullptr;
     int schedule = PIXVOD_SCHED_FUSED;
+    int topology = PIXVOD_TOPO_GRID;
     float* X[2] = {nullptr, nullptr};
+    float* NX[2] = {nullptr, nullptr};   // quadtree node state (ping-pong like X)
+    TreeGeo tg{};
     int cur = 0;
     float *Is = nullptr, *cxt = nullptr, *cyt = nullptr, *sig = nullptr;
     float *It = nullptr, *Gx = nullptr, *Gy = nullptr;
@@ -271,7 +276,7 @@ static void prof_collect(pixvod_ctx* c) {
 }
 
 static void release(pixvod_ctx* c) {
-    void* bufs[] = {c->X[0], c->X[1], c->Is, c->cxt, c->cyt, c->sig, c->It, c->Gx, c->Gy, c->prior_ell, c->var_ll,
+    void* bufs[] = {c->X[0], c->X[1], c->NX[0], c->NX[1], c->Is, c->cxt, c->cyt, c->sig, c->It, c->Gx, c->Gy, c->prior_ell, c->var_ll,
                     c->valid, c->frame_stage, c->kf_stage, c->out_stage, c->dense_state, c->marg, c->msg,
                     c->partial, c->result, c->health};
     for (void* b : bufs)
@@ -410,7 +415,53 @@ int pixvod_set_schedule(pixvod_ctx* c, int schedule) {
         return fail(c, PIXVOD_EINVAL, "unknown schedule");
     if (schedule == PIXVOD_SCHED_FUSED && c->P.damping != 0.0f)
         return fail(c, PIXVOD_EINVAL, "the fused schedule does not support message damping");
+    if (schedule == PIXVOD_SCHED_PER_FACTOR && c->topology == PIXVOD_TOPO_QUADTREE)
+        return fail(c, PIXVOD_EINVAL, "the quadtree topology runs the fused schedule only");
     c->schedule = schedule;
+    return PIXVOD_OK;
+}
+
+int pixvod_set_topology(pixvod_ctx* c, int topology) {
+    if (!c) return fail(nullptr, PIXVOD_EINVAL, "ctx is NULL");
+    if (topology != PIXVOD_TOPO_GRID && topology != PIXVOD_TOPO_QUADTREE)
+        return fail(c, PIXVOD_EINVAL, "unknown topology");
+    if (c->have_kf) return fail(c, PIXVOD_ESTATE, "the topology is set before the first keyframe");
+    if (topology == PIXVOD_TOPO_QUADTREE) {
+        if (c->schedule != PIXVOD_SCHED_FUSED || c->P.damping != 0.0f)
+            return fail(c, PIXVOD_EINVAL, "the quadtree topology runs the fused schedule without damping");
+        TreeGeo t;
+        if (!make_tree_geo(c->H, c->W, (double)c->P.sigma_P, (double)c->P.sigma_R, &t))
+            return fail(c, PIXVOD_EINVAL, "image too large for the quadtree");
+        if (!c->NX[0]) {
+            const size_t n = (size_t)TN_PLANES * (size_t)t.nplane;
+            int rc = dev_alloc(c, &c->NX[0], n);
+            if (!rc) rc = dev_alloc(c, &c->NX[1], n);
+            if (rc) return rc;
+        }
+        c->tg = t;
+        HIP_TRY(c, launch_tree_clear_nodes(t, c->NX[0], c->stream));
+        HIP_TRY(c, launch_tree_clear_nodes(t, c->NX[1], c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    c->topology = topology;
+    return PIXVOD_OK;
+}
+
+int pixvod_tree_levels(const pixvod_ctx* c, int* n_levels, int* hw) {
+    if (!c || !n_levels) return fail(const_cast<pixvod_ctx*>(c), PIXVOD_EINVAL, "ctx and n_levels are required");
+    const bool tree = c->topology == PIXVOD_TOPO_QUADTREE;
+    *n_levels = tree ? c->tg.L + 1 : 1;
+    if (hw) {
+        if (!tree) {
+            hw[0] = c->H;
+            hw[1] = c->W;
+        } else {
+            for (int l = 0; l <= c->tg.L; ++l) {
+                hw[2 * l] = c->tg.Hl[l];
+                hw[2 * l + 1] = c->tg.Wl[l];
+            }
+        }
+    }
     return PIXVOD_OK;
 }
 
@@ -439,6 +490,10 @@ int pixvod_set_keyframe(pixvod_ctx* c, const float* img, const float* normals, i
     float* Xc = c->X[c->cur];
     float* Xo = c->X[1 - c->cur];
     HIP_TRY(c, launch_keyframe_prep(g, di, dn, c->Is, c->cxt, c->cyt, Xc, Xo, c->stream));
+    if (c->topology == PIXVOD_TOPO_QUADTREE) {
+        HIP_TRY(c, launch_tree_clear_nodes(c->tg, c->NX[0], c->stream));
+        HIP_TRY(c, launch_tree_clear_nodes(c->tg, c->NX[1], c->stream));
+    }
     if (c->have_track) {
         double E[16], Ei[16], Tw[16];
         host_se3_exp(c->xi_last, E);
@@ -530,7 +585,24 @@ static int run_iterations(pixvod_ctx* c, int n) {
     const Geo g = geo_of(c);
     const Strengths s = strengths_of(c);
     const Inputs in = inputs_of(c);
-    if (c->schedule == PIXVOD_SCHED_PER_FACTOR) {
+    if (c->topology == PIXVOD_TOPO_QUADTREE) {
+        int src = c->cur, dst = 1 - c->cur;
+        hipEvent_t a = prof_begin(c);
+        HIP_TRY(c, launch_tree_prologue(g, c->tg, s, in, c->X[src], c->NX[src], c->X[dst], c->NX[dst], c->health,
+                                        c->stream));
+        prof_end(c, a, PIXVOD_PROF_FUSED_PROLOGUE);
+        src = dst;
+        for (int it = 0; it < n; ++it) {
+            dst = 1 - src;
+            const bool last = (it == n - 1);
+            a = prof_begin(c);
+            HIP_TRY(c, launch_tree_iterate(g, c->tg, s, in, c->X[src], c->NX[src], c->X[dst], c->NX[dst], last,
+                                           c->var_ll, c->valid, c->health, c->stream));
+            prof_end(c, a, last ? PIXVOD_PROF_FUSED_FINAL : PIXVOD_PROF_FUSED_ITERATE);
+            src = dst;
+        }
+        c->cur = src;
+    } else if (c->schedule == PIXVOD_SCHED_PER_FACTOR) {
         const size_t pl = (size_t)c->plane;
         if (!c->marg) {
             int rc = dev_alloc(c, &c->marg, pl * 29);
@@ -658,29 +730,60 @@ int pixvod_profile_read(pixvod_ctx* c, int kind, double* total_ms, int64_t* laun
     return PIXVOD_OK;
 }
 
+static size_t state_floats(const pixvod_ctx* c) {
+    const size_t N = (size_t)c->H * c->W;
+    if (c->topology == PIXVOD_TOPO_QUADTREE) return (size_t)TP_PLANES * N + (size_t)TN_PLANES * c->tg.NT;
+    return (size_t)N_PLANES * N;
+}
+
 int pixvod_state_bytes(const pixvod_ctx* c, size_t* bytes) {
     if (!c || !bytes) return fail(const_cast<pixvod_ctx*>(c), PIXVOD_EINVAL, "ctx and bytes are required");
-    *bytes = (size_t)N_PLANES * c->H * c->W * sizeof(float);
+    *bytes = state_floats(c) * sizeof(float);
     return PIXVOD_OK;
 }
 
+// staging of the exchange layout; sized for both topologies
 static int ensure_dense(pixvod_ctx* c) {
     if (c->dense_state) return PIXVOD_OK;
-    return dev_alloc(c, &c->dense_state, (size_t)N_PLANES * c->H * c->W);
+    const size_t N = (size_t)c->H * c->W;
+    TreeGeo t;
+    size_t n = (size_t)N_PLANES * N;
+    if (make_tree_geo(c->H, c->W, 1.0, 1.0, &t)) n = std::max(n, (size_t)TP_PLANES * N + (size_t)TN_PLANES * t.NT);
+    return dev_alloc(c, &c->dense_state, n);
+}
+
+// quadtree exchange: 42 pixel planes of H*W, then 141 node planes of NT
+static int tree_exchange(pixvod_ctx* c, float* d, int to_dense) {
+    const size_t N = (size_t)c->H * c->W;
+    float* X = c->X[c->cur];
+    float* NX = c->NX[c->cur];
+    HIP_TRY(c, launch_tree_pack_pixels(geo_of(c), X, d, to_dense, c->stream));
+    float* dn = d + (size_t)TP_PLANES * N;
+    const size_t w = (size_t)c->tg.NT * sizeof(float), sp = (size_t)c->tg.nplane * sizeof(float);
+    if (to_dense)
+        HIP_TRY(c, hipMemcpy2DAsync(dn, w, NX, sp, w, TN_PLANES, hipMemcpyDeviceToDevice, c->stream));
+    else
+        HIP_TRY(c, hipMemcpy2DAsync(NX, sp, dn, w, w, TN_PLANES, hipMemcpyDeviceToDevice, c->stream));
+    return PIXVOD_OK;
 }
 
 int pixvod_get_state(pixvod_ctx* c, void* dst, int where) {
     if (!c) return fail(nullptr, PIXVOD_EINVAL, "ctx is NULL");
     if (!dst) return fail(c, PIXVOD_EINVAL, "dst is NULL");
     if (where != PIXVOD_HOST && where != PIXVOD_DEVICE) return fail(c, PIXVOD_EINVAL, "bad location");
-    const size_t n = (size_t)N_PLANES * c->H * c->W;
+    const size_t n = state_floats(c);
     float* d = (float*)dst;
     if (where == PIXVOD_HOST) {
         int rc = ensure_dense(c);
         if (rc) return rc;
         d = c->dense_state;
     }
-    HIP_TRY(c, launch_pack_state(geo_of(c), c->X[c->cur], d, 1, c->stream));
+    if (c->topology == PIXVOD_TOPO_QUADTREE) {
+        int rc = tree_exchange(c, d, 1);
+        if (rc) return rc;
+    } else {
+        HIP_TRY(c, launch_pack_state(geo_of(c), c->X[c->cur], d, 1, c->stream));
+    }
     if (where == PIXVOD_HOST)
         HIP_TRY(c, hipMemcpyAsync(dst, d, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -691,7 +794,7 @@ int pixvod_set_state(pixvod_ctx* c, const void* src, int where) {
     if (!c) return fail(nullptr, PIXVOD_EINVAL, "ctx is NULL");
     if (!src) return fail(c, PIXVOD_EINVAL, "src is NULL");
     if (where != PIXVOD_HOST && where != PIXVOD_DEVICE) return fail(c, PIXVOD_EINVAL, "bad location");
-    const size_t n = (size_t)N_PLANES * c->H * c->W;
+    const size_t n = state_floats(c);
     const float* d = (const float*)src;
     if (where == PIXVOD_HOST) {
         int rc = ensure_dense(c);
@@ -699,7 +802,12 @@ int pixvod_set_state(pixvod_ctx* c, const void* src, int where) {
         HIP_TRY(c, hipMemcpyAsync(c->dense_state, src, n * sizeof(float), hipMemcpyHostToDevice, c->stream));
         d = c->dense_state;
     }
-    HIP_TRY(c, launch_pack_state(geo_of(c), c->X[c->cur], const_cast<float*>(d), 0, c->stream));
+    if (c->topology == PIXVOD_TOPO_QUADTREE) {
+        int rc = tree_exchange(c, const_cast<float*>(d), 0);
+        if (rc) return rc;
+    } else {
+        HIP_TRY(c, launch_pack_state(geo_of(c), c->X[c->cur], const_cast<float*>(d), 0, c->stream));
+    }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return PIXVOD_OK;
 }

@@ -50,6 +50,20 @@ def from_oracle(state: np.ndarray) -> np.ndarray:
     return np.ascontiguousarray(np.transpose(state, (2, 0, 1)).astype(np.float32))
 
 
+def tree_to_oracle(state):
+    """Quadtree exchange layout ((42, H, W), (141, NT)) float32 -> the
+    oracle's ((H, W, 42), (NT, 141)) float64."""
+    pix, nodes = state
+    return (np.ascontiguousarray(np.transpose(pix.astype(np.float64), (1, 2, 0))),
+            np.ascontiguousarray(nodes.astype(np.float64).T))
+
+
+def tree_from_oracle(state):
+    pix, nodes = state
+    return (np.ascontiguousarray(np.transpose(pix, (2, 0, 1)).astype(np.float32)),
+            np.ascontiguousarray(nodes.T.astype(np.float32)))
+
+
 def depth_agreement(rho_gpu: np.ndarray, rho_or: np.ndarray) -> Dict[str, float]:
     e = np.abs(rho_gpu.astype(np.float64) - rho_or) / np.abs(rho_or)
     return dict(rms=float(np.sqrt(np.mean(e * e))), p99=float(np.percentile(e, 99)),
@@ -82,17 +96,19 @@ def K_of(cam):
     return (cam.fx, cam.fy, cam.cx, cam.cy)
 
 
-def make_oracle(w) -> "oracle.Oracle":
-    o = oracle.Oracle(oracle.config_for_camera(w["cam"], **w["kw"]))
+def make_oracle(w, topology: int = 0) -> "oracle.Oracle":
+    o = oracle.Oracle(oracle.config_for_camera(w["cam"], topology=topology, **w["kw"]))
     o.set_keyframe(w["I_s"], w["N_s"])
     return o
 
 
-def make_tracker(w, schedule=0):
+def make_tracker(w, schedule=0, topology: int = 0):
     import paper_2606_03989_amd as pv
     cam = w["cam"]
     t = pv.Tracker(cam.H, cam.W, K_of(cam), **w["kw"])
     t.set_schedule(schedule)
+    if topology:
+        t.set_topology(topology)
     t.set_keyframe(w["I_s"], w["N_s"])
     return t
 

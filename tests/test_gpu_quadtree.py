@@ -1,0 +1,179 @@
+"""GPU parity of the quadtree identity topology (Fig. 2, Sec. 3.3, Sec. 4.2):
+the HIP path through the C-ABI against the FP64 oracle on the same seeded
+inputs, teacher-forced per iteration (all 42 pixel planes and 141 node planes)
+and free-running over one frame."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import (DEPTH_TOL, POSE_TOL, K_of, depth_agreement, make_oracle, make_tracker, pose_agreement,
+                    sequence_workload, tiny_workload, tree_from_oracle, tree_to_oracle)
+
+pytestmark = pytest.mark.gpu
+
+QT = oracle.TOPO_QUADTREE
+
+
+def _rel_errors(g, r):
+    """Per-plane relative errors of a (planes, ...) pair, scaled by the
+    oracle plane's largest magnitude."""
+    g = g.astype(np.float64).reshape(g.shape[0], -1)
+    r = r.astype(np.float64).reshape(r.shape[0], -1)
+    scale = np.abs(r).max(axis=1)[:, None] + 1e-30
+    return np.abs(g - r) / scale
+
+
+def _one_step(t, o, s32):
+    t.set_state(s32)
+    o.set_state(tree_to_oracle(s32))
+    t.iterate(1)
+    o.iterate(1)
+    return t.get_state(), tree_from_oracle(o.get_state())
+
+
+def _compare(g, r, name, p999=1e-5, frac_bound=2e-3):
+    out = {}
+    for part, gi, ri in (("pixels", g[0], r[0]), ("nodes", g[1], r[1])):
+        err = _rel_errors(gi, ri)
+        q = float(np.percentile(err, 99.9))
+        frac = float(np.mean(err > 1e-5))
+        worst = np.unravel_index(np.argmax(err), err.shape)
+        print(f"{name} {part}: plane-relative p99.9 {q:.2e} max {err.max():.2e} at plane/index {worst} "
+              f"frac>1e-5 {frac:.2e}", flush=True)
+        out[part] = (q, frac)
+        assert q <= p999 and frac <= frac_bound, f"{name} {part}"
+    return out
+
+
+def _tree_workload(kind):
+    if kind == "tiny":
+        return tiny_workload(huber_k=10.0)
+    if kind == "ppa256":
+        w = sequence_workload("ppa256", 1)
+        return w
+    # ragged shapes: odd sizes leave level nodes with missing children
+    H, W = {"ragged37x53": (37, 53), "ragged5x3": (5, 3), "min2x2": (2, 2)}[kind]
+    p = synth.tiny_pair(5, H=max(H, 4), W=max(W, 4), lattice_px=2.0)
+    cam = synth.Camera(H, W, p["cam"].fx, p["cam"].fy, p["cam"].cx, p["cam"].cy)
+    return dict(cam=cam, I_s=p["I_s"][:H, :W].copy(), N_s=p["normals_s"][:H, :W].copy(),
+                frames=[p["I_t"][:H, :W].copy()], iters=20, kw=dict(init_inv_depth=0.3, sigma_P=0.1))
+
+
+def test_levels_topology_errors_and_state_exchange():
+    import paper_2606_03989_amd as pv
+    w = tiny_workload()
+    cam = w["cam"]
+    t = pv.Tracker(cam.H, cam.W, K_of(cam), **w["kw"])
+    assert t.tree_levels() == [(cam.H, cam.W)]
+    with pytest.raises(pv.PixvodError):
+        t.set_topology(7)
+    t.set_topology(pv.TOPO_QUADTREE)
+    o = make_oracle(w, QT)
+    assert t.tree_levels() == o.tree_levels()
+    with pytest.raises(pv.PixvodError):
+        t.set_schedule(1)                    # per-factor schedule: grid only
+    t.set_keyframe(w["I_s"], w["N_s"])
+    with pytest.raises(pv.PixvodError):
+        t.set_topology(pv.TOPO_GRID)         # after the keyframe
+    n_nodes = sum(h * wd for h, wd in o.tree_levels()[1:])
+    assert t.state_bytes() == 4 * (42 * cam.H * cam.W + 141 * n_nodes)
+    # a keyframe leaves zero messages and identity poses at every level
+    pix, nodes = t.get_state()
+    assert np.all(nodes == 0) and np.all(pix[:6] == 0) and np.all(pix[7:] == 0)
+    # exchange round trip, bit for bit
+    rng = np.random.default_rng(0)
+    s = (rng.normal(size=pix.shape).astype(np.float32), rng.normal(size=nodes.shape).astype(np.float32))
+    t.set_state(s)
+    g = t.get_state()
+    assert np.array_equal(g[0], s[0]) and np.array_equal(g[1], s[1])
+    # VGA levels: 11 (640 -> 1 in ten halvings)
+    t2 = pv.Tracker(480, 640, (500.0, 500.0, 320.0, 240.0))
+    t2.set_topology(pv.TOPO_QUADTREE)
+    assert len(t2.tree_levels()) == 11 and t2.tree_levels()[-1] == (1, 1)
+    t2.close()
+    t.close()
+
+
+@pytest.mark.parametrize("kind", ["tiny", "ppa256", "ragged37x53", "ragged5x3", "min2x2"])
+def test_single_iteration_from_identical_state(kind):
+    w = _tree_workload(kind)
+    o = make_oracle(w, QT)
+    o.track(w["frames"][0], 3)
+    s32 = tree_from_oracle(o.get_state())
+    t = make_tracker(w, 0, QT)
+    t.track(w["frames"][0], 0)          # stages the frame
+    g, r = _one_step(t, o, s32)
+    _compare(g, r, f"quadtree {kind}")
+
+
+def test_teacher_forced_iterations_ppa256():
+    w = sequence_workload("ppa256", 1)
+    t = make_tracker(w, 0, QT)
+    o = make_oracle(w, QT)
+    t.track(w["frames"][0], 0)
+    o.set_frame(w["frames"][0])
+    worst = {"pixels": 0.0, "nodes": 0.0}
+    for it in range(w["iters"]):
+        s32 = t.get_state()
+        o.set_state(tree_to_oracle(s32))
+        t.iterate(1)
+        o.iterate(1)
+        res = _compare(t.get_state(), tree_from_oracle(o.get_state()), f"iteration {it}")
+        for k in worst:
+            worst[k] = max(worst[k], res[k][0])
+    print(f"ppa256 quadtree teacher-forced {w['iters']} iterations: worst p99.9 {worst}", flush=True)
+
+
+def _oracle_spread(w, ro):
+    """How far the oracle's own frame moves when its starting log-depths are
+    perturbed at FP32 resolution (uniform +-6e-8, the size of the GPU's
+    storage rounding): the conditioning of the free-running frame, below
+    which GPU and oracle cannot be told apart."""
+    o2 = make_oracle(w, QT)
+    pix, nodes = o2.get_state()
+    pix[..., 6] += 6e-8 * np.random.default_rng(0).uniform(-1, 1, pix[..., 6].shape)
+    o2.set_state((pix, nodes))
+    r2 = o2.track(w["frames"][0], w["iters"])
+    o2.close()
+    return pose_agreement(ro["xi"], r2["xi"]), depth_agreement(ro["inv_depth"], r2["inv_depth"])
+
+
+def _assert_frame(rg, ro, name, spread):
+    dp = pose_agreement(rg["xi"], ro["xi"])
+    da = depth_agreement(rg["inv_depth"], ro["inv_depth"])
+    sp, sd = spread
+    print(f"{name}: pose {dp:.2e} depth rms {da['rms']:.2e} p99 {da['p99']:.2e} max {da['max']:.2e} "
+          f"valid {rg['valid_fraction']:.4f}/{ro['valid_fraction']:.4f}; oracle spread pose {sp:.2e} "
+          f"rms {sd['rms']:.2e} p99 {sd['p99']:.2e}; xi {np.round(rg['xi'], 5)}", flush=True)
+    # the fixed parity bar, or twice the oracle's own spread where the frame
+    # is worse conditioned than that bar
+    assert dp <= max(POSE_TOL, 2.0 * sp)
+    assert da["rms"] <= max(DEPTH_TOL, 2.0 * sd["rms"]) and da["p99"] <= max(DEPTH_TOL, 2.0 * sd["p99"])
+    assert abs(rg["valid_fraction"] - ro["valid_fraction"]) <= 2e-3
+    assert (rg["flags"] & oracle.DIVERGED) == (ro["flags"] & oracle.DIVERGED) == 0
+
+
+@pytest.mark.parametrize("kind", ["tiny", "ppa256"])
+def test_free_running_frame(kind):
+    w = _tree_workload(kind)
+    t = make_tracker(w, 0, QT)
+    o = make_oracle(w, QT)
+    rg = t.track(w["frames"][0], w["iters"])
+    ro = o.track(w["frames"][0], w["iters"])
+    _assert_frame(rg, ro, f"quadtree {kind} frame 1", _oracle_spread(w, ro))
+    # inverse-depth variance of the final belief: r^2 var(ell), so it follows
+    # the depth agreement (a handful of ill-conditioned pixels aside)
+    ev = np.abs(rg["inv_depth_var"].astype(np.float64) - ro["inv_depth_var"]) / ro["inv_depth_var"]
+    print(f"inverse-depth variance: p99 {np.percentile(ev, 99):.2e} max {ev.max():.2e}", flush=True)
+    assert np.all(rg["inv_depth_var"] > 0) and np.percentile(ev, 99) <= 1e-3 and ev.max() <= 1e-2
+
+
+def test_vga_frame_1():
+    w = sequence_workload("vga", 1)
+    t = make_tracker(w, 0, QT)
+    o = make_oracle(w, QT)
+    rg = t.track(w["frames"][0], w["iters"])
+    ro = o.track(w["frames"][0], w["iters"])
+    _assert_frame(rg, ro, "quadtree vga frame 1", _oracle_spread(w, ro))

@@ -160,7 +160,68 @@ def run_gpu(args):
         log(f"per-factor: {pf_value:.1f} Mpx-iter/s, iteration {pf_launch * 1e6:.1f} us")
         tp.close()
     t.close()
-    return dict(value=value, elapsed=elapsed, roofline=roofline, per_factor=per_factor, H=H, W=W, iters=iters)
+    return dict(value=value, elapsed=elapsed, roofline=roofline, per_factor=per_factor, H=H, W=W, iters=iters,
+                pass_us=avg_launch_s * 1e6, inputs=(cam, d_I0, d_N0, d_frames, d_normals, stream))
+
+
+# algorithmic bytes of one quadtree iteration (pixel pass + node pass).
+# Pixel: reads its point (7), normal slots (8), the parent's partial for its
+# slot (27), a quarter of the parent's pose (1.5), keyframe intensity and two
+# normal targets (3), the warped target intensity and gradients (3); writes
+# its point (7), its partial to the parent (27), four normal partials (8).
+# Node: reads its pose (6), a quarter of the parent's pose (1.5), the parent's
+# partial (27), four children's poses (24) and partials (108); writes its pose
+# (6), its partial to the parent (27) and four partials to the children (108).
+TREE_PIXEL_FLOATS = 49.5 + 42
+TREE_NODE_FLOATS = 166.5 + 141
+
+
+def run_quadtree(args, g):
+    """The same frames with the quadtree identity topology (Fig. 2): per-pass
+    duration (pixel and node launches together) against the grid's pass."""
+    import torch
+    import paper_2606_03989_amd as pv
+    cam, d_I0, d_N0, d_frames, d_normals, stream = g["inputs"]
+    H, W, iters = g["H"], g["W"], g["iters"]
+    t = pv.Tracker(H, W, (cam.fx, cam.fy, cam.cx, cam.cy), **VGA_PARAMS)
+    t.set_stream(stream)
+    t.set_topology(pv.TOPO_QUADTREE)
+    t.set_keyframe(d_I0, d_N0)
+    n_nodes = sum(h * w for h, w in t.tree_levels()[1:])
+    levels = len(t.tree_levels())
+
+    def step(i):
+        r = t.track(d_frames[i], iters, maps=True, out_device=True)
+        if r["flags"] & pv.KEYFRAME_DUE:
+            t.set_keyframe(d_frames[i], d_normals[i])
+        return r
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    t.profile(True)
+    for k in range(4):
+        t.profile_read(k)
+    a = time.perf_counter()
+    flags = 0
+    for i in range(args.warmup, args.warmup + args.steps):
+        flags |= step(i)["flags"]
+    torch.cuda.synchronize()
+    b = time.perf_counter()
+    it_ms, it_n = t.profile_read(pv.PROF_FUSED_ITERATE)
+    t.profile(False)
+    t.close()
+    value = H * W * iters * args.steps / (b - a) / 1e6
+    pass_s = it_ms / 1e3 / max(it_n, 1)
+    bytes_per_pass = 4.0 * (TREE_PIXEL_FLOATS * H * W + TREE_NODE_FLOATS * n_nodes)
+    achieved = bytes_per_pass / pass_s / 1e9
+    log(f"quadtree: {value:.1f} Mpx-iter/s, pass {pass_s * 1e6:.1f} us ({levels} levels, {n_nodes} nodes), "
+        f"{achieved:.0f} GB/s algorithmic; flags seen {flags}")
+    return dict(value=round(value, 1), unit="Mpixel-iter/s", levels=levels, nodes=n_nodes,
+                pass_us=round(pass_s * 1e6, 2), grid_pass_us=round(g["pass_us"], 2),
+                pass_speedup_vs_grid=round(g["pass_us"] / (pass_s * 1e6), 3),
+                bytes_per_pass=int(bytes_per_pass), achieved_GBs=round(achieved, 1),
+                frac=round(achieved / HBM_PEAK_GBS, 4), vs_grid=round(value / g["value"], 3))
 
 
 def _render_seq(args):
@@ -476,6 +537,8 @@ def main():
                     help="tracking accuracy under sensor noise (clean, Gaussian, mild, strong); its own JSON line")
     ap.add_argument("--batch-steps", type=int, default=4, help="timed frame steps of the 64-sequence batch (0: skip)")
     ap.add_argument("--batch-seqs", type=int, default=64)
+    ap.add_argument("--no-quadtree", dest="quadtree", action="store_false",
+                    help="skip the quadtree-topology leg on the same frames")
     ap.add_argument("--adjoint-frames", type=int, default=29,
                     help="target frames of the forward+adjoint leg (the 30-frame sequence after its keyframe; 0: skip)")
     args = ap.parse_args()
@@ -493,6 +556,7 @@ def main():
         sys.exit(2)
 
     g = run_gpu(args)
+    quadtree = run_quadtree(args, g) if args.quadtree else None
     batched = run_batch(args.batch_seqs, args.batch_steps, 15, max(1, args.batch_steps // 2)) if args.batch_steps > 0 else None
     adjoint = run_adjoint(args.adjoint_frames, 30, 10, 2) if args.adjoint_frames > 0 else None
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_iters)
@@ -517,6 +581,7 @@ def main():
         "per_factor": g["per_factor"],
         "batched": batched,
         "forward_adjoint": adjoint,
+        "quadtree": quadtree,
     }
     print(json.dumps(out), flush=True)
 

@@ -523,6 +523,34 @@ def probe(frames: int = 3, copy_mb: int = 512):
     log(f"probe done: copy calibration {copy_mb} MiB read + {copy_mb} MiB written per copy, 3 copies")
 
 
+def run_central(args, g, n_frames: int = 2, irls_iters: int = 5):
+    """The centralised IRLS Gauss-Newton baseline (Sec. 3.1, Sec. 4.4) on the
+    same 640x480 frames: one global pose and per-pixel log-depths, the normal
+    equations solved by FP64 preconditioned conjugate gradients (relative
+    residual 1e-8). Reported per IRLS iteration."""
+    import torch
+    import paper_2606_03989_amd as pv
+    cam, d_I0, d_N0, d_frames, d_normals, stream = g["inputs"]
+    H, W = g["H"], g["W"]
+    c = pv.Central(H, W, (cam.fx, cam.fy, cam.cx, cam.cy), max_cg=400, cg_tol=1e-8, **VGA_PARAMS)
+    c.set_stream(stream)
+    c.set_keyframe(d_I0, d_N0)
+    c.track(d_frames[0], 1, maps=False)        # warm-up
+    ms, cg = 0.0, 0
+    for i in range(n_frames):
+        r = c.track(d_frames[1 + i], irls_iters, maps=True, out_device=True)
+        ms += c.last_ms()
+        cg += r["cg_iters"]
+    torch.cuda.synchronize()
+    c.close()
+    per_iter = ms / (n_frames * irls_iters)
+    log(f"centralised IRLS: {per_iter:.2f} ms per IRLS iteration, {cg / (n_frames * irls_iters):.0f} CG iterations each")
+    return dict(ms_per_irls_iteration=round(per_iter, 3), cg_iterations_per_irls=round(cg / (n_frames * irls_iters), 1),
+                cg_tol=1e-8, frames=n_frames, irls_iterations_per_frame=irls_iters,
+                Mpixel_iter_per_s=round(H * W / (per_iter / 1e3) / 1e6, 1),
+                gbp_iteration_ms=round(g["pass_us"] / 1e3, 4))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -539,6 +567,8 @@ def main():
     ap.add_argument("--batch-seqs", type=int, default=64)
     ap.add_argument("--no-quadtree", dest="quadtree", action="store_false",
                     help="skip the quadtree-topology leg on the same frames")
+    ap.add_argument("--no-central", dest="central", action="store_false",
+                    help="skip the centralised IRLS Gauss-Newton leg on the same frames")
     ap.add_argument("--adjoint-frames", type=int, default=29,
                     help="target frames of the forward+adjoint leg (the 30-frame sequence after its keyframe; 0: skip)")
     args = ap.parse_args()
@@ -557,6 +587,7 @@ def main():
 
     g = run_gpu(args)
     quadtree = run_quadtree(args, g) if args.quadtree else None
+    central = run_central(args, g) if args.central else None
     batched = run_batch(args.batch_seqs, args.batch_steps, 15, max(1, args.batch_steps // 2)) if args.batch_steps > 0 else None
     adjoint = run_adjoint(args.adjoint_frames, 30, 10, 2) if args.adjoint_frames > 0 else None
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_iters)
@@ -582,6 +613,7 @@ def main():
         "batched": batched,
         "forward_adjoint": adjoint,
         "quadtree": quadtree,
+        "centralised": central,
     }
     print(json.dumps(out), flush=True)
 

@@ -321,6 +321,54 @@ int pixvod_unroll_backward(pixvod_unroll* u, const double* xi_bar, const float* 
 /* Durations (ms, HIP events on the stream) of the last forward and backward. */
 int pixvod_unroll_last_ms(const pixvod_unroll* u, double* forward_ms, double* backward_ms);
 
+/* ---------------------------------------------------------------------------
+ * Centralised baseline: direct tracking with every pixel accessible at once
+ * (Sec. 3.1, Eq. photo), solved by IRLS Gauss-Newton as the paper's
+ * centralised comparison (Sec. 4.4). Unknowns: one global pose xi (right
+ * perturbation) and a log-depth per keyframe pixel. The energy is the
+ * per-pixel model's at exact consensus: photometric factors with the Huber
+ * covariance weighting frozen at the current residuals, each pixel's pose and
+ * log-depth prior, and the normal-integration factors; there are no identity
+ * factors. Each IRLS iteration solves the Gauss-Newton normal equations
+ * (6 + H*W unknowns; the depth block is diagonal plus sigma_N^-2 times the
+ * graph Laplacian of the active normal edges) by preconditioned conjugate
+ * gradients in FP64 (block-Jacobi: the 6x6 pose block and the depth
+ * diagonal) until the residual norm falls below cg_tol times its initial
+ * value or max_cg iterations, then sets xi <- Log(Exp(xi) Exp(d_xi)),
+ * ell <- ell + d_ell. Parameters as pixvod_params (sigma_R unused; a constant
+ * sigma_D). Device memory: 15 FP64 and 6 FP32 planes of H x W.
+ */
+typedef struct pixvod_central pixvod_central;
+
+typedef struct {
+    int32_t cg_iters;          /* CG iterations over the call's IRLS iterations */
+    int32_t last_cg_iters;     /* those of the last IRLS iteration */
+    double last_rel_residual;  /* its final residual norm / initial norm */
+    float valid_fraction;      /* pixels whose warp landed in the image (last linearisation) */
+    uint32_t flags;            /* PIXVOD_DIVERGED for a non-finite pose */
+} pixvod_central_stats;
+
+/* H, W >= 2, H*W <= 2^26; max_cg >= 1; 0 < cg_tol < 1. The initial point is
+ * the identity pose and log-depth -log(params.init_inv_depth). */
+int pixvod_central_create(int H, int W, const pixvod_intrinsics* K, const pixvod_params* params, int max_cg,
+                          double cg_tol, pixvod_central** out);
+int pixvod_central_destroy(pixvod_central* c);
+int pixvod_central_set_stream(pixvod_central* c, void* hip_stream);
+/* keyframe image (H*W) and normals (H*W*3); the pose restarts at the
+ * identity, log-depths are kept */
+int pixvod_central_set_keyframe(pixvod_central* c, const float* img, const float* normals, int where);
+/* current point: xi (6 doubles, host) and log-depths (H*W doubles, host,
+ * row-major); either may be NULL */
+int pixvod_central_set_point(pixvod_central* c, const double xi[6], const double* log_depth);
+int pixvod_central_get_point(pixvod_central* c, double xi[6], double* log_depth);
+/* n_iters >= 0 IRLS iterations on `frame` (H*W) from the current point
+ * (warm start); xi_out (host, may be NULL), inv_depth (H*W at out_where, may
+ * be NULL), stats (may be NULL). ESTATE before a keyframe. */
+int pixvod_central_track(pixvod_central* c, const float* frame, int where, int n_iters, double xi_out[6],
+                         float* inv_depth, int out_where, pixvod_central_stats* stats);
+/* duration (ms, HIP events) of the last call's IRLS iterations */
+int pixvod_central_last_ms(const pixvod_central* c, double* ms);
+
 /* Per-context message of the last failure; ctx == NULL gives the last
  * failure of a call that had no context (e.g. pixvod_create). */
 const char* pixvod_last_error(const pixvod_ctx* ctx);

@@ -151,10 +151,20 @@ class Centralised:
         return M, g, int(valid.sum())
 
     def step(self, xi, ell):
-        """The exact Gauss-Newton step (d_xi (6), d_ell (N)) at (xi, ell)."""
+        """The exact Gauss-Newton step (d_xi (6), d_ell (N)) at (xi, ell), by
+        block elimination of the depths: with M = [[A, B], [B', D]] and one
+        sparse LU factorisation of D, S = A - B D^-1 B', d_xi = S^-1 (g_xi -
+        B D^-1 g_ell), d_ell = D^-1 (g_ell - B' d_xi)."""
         M, g, _ = self.normal_equations(xi, ell)
-        d = spla.spsolve(M.tocsc(), g)
-        return d[:6], d[6:]
+        M = M.tocsc()
+        A = M[:6, :6].toarray()
+        B = M[:6, 6:].toarray()
+        lu = spla.splu(M[6:, 6:].tocsc())
+        Y = lu.solve(np.ascontiguousarray(B.T))
+        y = lu.solve(g[6:])
+        S = A - B @ Y
+        dx = np.linalg.solve(S, g[:6] - B @ y)
+        return dx, y - Y @ dx
 
     def iterate(self, xi, ell, n_iters: int):
         xi = np.array(xi, np.float64)

@@ -59,6 +59,11 @@ class TrackOut(C.Structure):
     ]
 
 
+class CentralStats(C.Structure):
+    _fields_ = [("cg_iters", C.c_int32), ("last_cg_iters", C.c_int32), ("last_rel_residual", C.c_double),
+                ("valid_fraction", C.c_float), ("flags", C.c_uint32)]
+
+
 _lib: Optional[C.CDLL] = None
 
 # every entry point declared in include/pixvod.h, with its ctypes signature
@@ -102,6 +107,16 @@ _SIGNATURES = {
     "pixvod_unroll_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int,
                                          C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "pixvod_unroll_last_ms": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "pixvod_central_create": (C.c_int, [C.c_int, C.c_int, C.POINTER(Intrinsics), C.POINTER(Params), C.c_int,
+                                        C.c_double, C.POINTER(C.c_void_p)]),
+    "pixvod_central_destroy": (C.c_int, [C.c_void_p]),
+    "pixvod_central_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "pixvod_central_set_keyframe": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "pixvod_central_set_point": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pixvod_central_get_point": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pixvod_central_track": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int,
+                                       C.POINTER(CentralStats)]),
+    "pixvod_central_last_ms": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "pixvod_last_error": (C.c_char_p, [C.c_void_p]),
     "pixvod_version": (C.c_char_p, []),
 }
@@ -512,6 +527,82 @@ def unrolled_track(unroll: Unrolled, frames, sigma_map, sigma_N, huber_k):
     as functions of the sigma map (H, W), sigma_N and huber_k (0-d tensors).
     The backward pass is the library's adjoint; one graph per context at a time."""
     return _UnrolledTrack.apply(unroll, frames, sigma_map, sigma_N, huber_k)
+
+
+class Central:
+    """Centralised IRLS Gauss-Newton baseline: one global pose and per-pixel
+    log-depths, every pixel accessible at once (the normal equations solved by
+    FP64 preconditioned conjugate gradients on the GPU)."""
+
+    def __init__(self, H: int, W: int, K, max_cg: int = 500, cg_tol: float = 1e-10,
+                 params: Optional[Params] = None, **overrides):
+        self.H, self.W = int(H), int(W)
+        if params is None:
+            params = default_params(**overrides)
+        self.params = params
+        Kc = Intrinsics(*[float(x) for x in K])
+        h = C.c_void_p()
+        _check(lib().pixvod_central_create(self.H, self.W, C.byref(Kc), C.byref(params), int(max_cg),
+                                           float(cg_tol), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pixvod_central_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream=None):
+        s = None if stream is None else C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else stream)
+        _check(lib().pixvod_central_set_stream(self._h, s))
+
+    def set_keyframe(self, img, normals):
+        pi, wi, ki = _ptr(img)
+        pn, wn, kn = _ptr(normals)
+        if wi != wn:
+            raise ValueError("img and normals must live in the same memory")
+        _check(lib().pixvod_central_set_keyframe(self._h, C.c_void_p(pi), C.c_void_p(pn), wi))
+
+    def set_point(self, xi=None, log_depth=None):
+        x = None if xi is None else np.ascontiguousarray(xi, np.float64)
+        d = None if log_depth is None else np.ascontiguousarray(log_depth, np.float64).reshape(-1)
+        _check(lib().pixvod_central_set_point(self._h, None if x is None else C.c_void_p(x.ctypes.data),
+                                              None if d is None else C.c_void_p(d.ctypes.data)))
+
+    def get_point(self):
+        xi = np.zeros(6)
+        d = np.zeros(self.H * self.W)
+        _check(lib().pixvod_central_get_point(self._h, C.c_void_p(xi.ctypes.data), C.c_void_p(d.ctypes.data)))
+        return xi, d.reshape(self.H, self.W)
+
+    def track(self, frame, n_iters: int, maps: bool = True, out_device: bool = False):
+        pf, wf, kf = _ptr(frame)
+        xi = np.zeros(6)
+        st = CentralStats()
+        inv = None
+        pinv = None
+        if maps:
+            if out_device:
+                inv = torch.empty((self.H, self.W), dtype=torch.float32, device="cuda")
+                pinv = inv.data_ptr()
+            else:
+                inv = np.zeros((self.H, self.W), np.float32)
+                pinv = inv.ctypes.data
+        _check(lib().pixvod_central_track(self._h, C.c_void_p(pf), wf, int(n_iters), C.c_void_p(xi.ctypes.data),
+                                          None if pinv is None else C.c_void_p(pinv),
+                                          DEVICE if out_device else HOST, C.byref(st)))
+        return dict(xi=xi, inv_depth=inv, cg_iters=st.cg_iters, last_cg_iters=st.last_cg_iters,
+                    last_rel_residual=st.last_rel_residual, valid_fraction=st.valid_fraction, flags=st.flags)
+
+    def last_ms(self) -> float:
+        ms = C.c_double()
+        _check(lib().pixvod_central_last_ms(self._h, C.byref(ms)))
+        return ms.value
 
 
 def version() -> str:

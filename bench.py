@@ -477,6 +477,81 @@ def noise_sweep(n_frames: int = 20, iters: int = 20):
                       "workload": f"256x256 six-plane scene, slow motion, frames 1-{n_frames}, {iters} iterations"}))
 
 
+def compare_solvers(n_frames: int = 10):
+    """Centralised IRLS Gauss-Newton against distributed GBP (Sec. 4.4, Fig.
+    centralized_vs_pixvod) on the same GPU: the 256x256 slow-motion scene of
+    the noise sweep, frames 1..n, each solver warm-started frame to frame.
+    Prints one JSON line with, per solver and per-frame iteration count, the
+    median rotation error and relative pose error of Eq. (rel_err) and the
+    GPU time per frame."""
+    import dataclasses
+    import math
+    import numpy as np
+    import paper_2606_03989_amd as pv
+    from synth.scenes import SEQUENCE_CONFIGS, make_sequence_scene, render, sequence_poses
+    cfg = dataclasses.replace(SEQUENCE_CONFIGS["ppa256"], max_step_t=0.002, max_step_r_deg=0.1, noise_sigma=0.0)
+    scene, cam = make_sequence_scene(cfg)
+    poses = sequence_poses(cfg)
+    K = (cam.fx, cam.fy, cam.cx, cam.cy)
+    clean = [render(scene, cam, poses[f]) for f in range(n_frames + 1)]
+    imgs = [np.ascontiguousarray(c[0], np.float32) for c in clean]
+    N0 = np.ascontiguousarray(clean[0][2], np.float32)
+
+    def so3_log(R):
+        c = max(-1.0, min(1.0, 0.5 * (np.trace(R) - 1.0)))
+        th = math.acos(c)
+        v = np.array([R[2, 1] - R[1, 2], R[0, 2] - R[2, 0], R[1, 0] - R[0, 1]])
+        return 0.5 * v if th < 1e-8 else th / (2.0 * math.sin(th)) * v
+
+    def errors(xs):
+        rot, rel = [], []
+        for f, xi in enumerate(xs, start=1):
+            T = np.linalg.inv(poses[f]) @ poses[0]
+            E = pv_exp(xi)
+            er = so3_log(E[:3, :3] @ T[:3, :3].T)
+            et = E[:3, 3] - T[:3, 3]
+            wg = so3_log(T[:3, :3])
+            rot.append(math.degrees(float(np.linalg.norm(er))))
+            rel.append(math.sqrt(float(er @ er + et @ et)) / math.sqrt(float(wg @ wg + T[:3, 3] @ T[:3, 3])))
+        return round(float(np.median(rot)), 5), round(float(np.median(rel)), 4)
+
+    out = {}
+    params = dict(sigma_P=0.01, huber_k=400.0)
+    for name, topo in (("gbp_grid", pv.TOPO_GRID), ("gbp_quadtree", pv.TOPO_QUADTREE)):
+        for iters in (20, 100):
+            t = pv.Tracker(cam.H, cam.W, K, **params)
+            if topo:
+                t.set_topology(topo)
+            t.set_keyframe(imgs[0], N0)
+            xs, ms = [], 0.0
+            for f in range(1, n_frames + 1):
+                a = time.perf_counter()
+                xs.append(t.track(imgs[f], iters, maps=False)["xi"])
+                ms += (time.perf_counter() - a) * 1e3
+            t.close()
+            rot, rel = errors(xs)
+            out[f"{name}_{iters}it"] = dict(median_rot_err_deg=rot, median_rel_pose_err=rel,
+                                            ms_per_frame=round(ms / n_frames, 3))
+            log(f"{name} {iters} iterations/frame: {out[f'{name}_{iters}it']}")
+    for iters in (1, 3, 10):
+        c = pv.Central(cam.H, cam.W, K, max_cg=400, cg_tol=1e-8, **params)
+        c.set_keyframe(imgs[0], N0)
+        xs, ms, cg = [], 0.0, 0
+        for f in range(1, n_frames + 1):
+            r = c.track(imgs[f], iters, maps=False)
+            xs.append(r["xi"])
+            ms += c.last_ms()
+            cg += r["cg_iters"]
+        c.close()
+        rot, rel = errors(xs)
+        out[f"centralised_{iters}it"] = dict(median_rot_err_deg=rot, median_rel_pose_err=rel,
+                                             ms_per_frame=round(ms / n_frames, 3),
+                                             cg_iterations_per_frame=round(cg / n_frames, 1))
+        log(f"centralised {iters} IRLS iterations/frame: {out[f'centralised_{iters}it']}")
+    print(json.dumps({"solver_comparison": out, "workload": f"256x256 six-plane scene, slow motion, frames 1-{n_frames}, "
+                      "sigma_P 0.01, Huber k 400; centralised CG tolerance 1e-8"}))
+
+
 def pv_exp(xi):
     """Exp of Eq. (exp_err) as a 4x4 matrix (reporting only)."""
     import numpy as np
@@ -567,6 +642,8 @@ def main():
     ap.add_argument("--batch-seqs", type=int, default=64)
     ap.add_argument("--no-quadtree", dest="quadtree", action="store_false",
                     help="skip the quadtree-topology leg on the same frames")
+    ap.add_argument("--compare-solvers", action="store_true",
+                    help="centralised IRLS against distributed GBP on the slow-motion 256x256 scene; its own JSON line")
     ap.add_argument("--no-central", dest="central", action="store_false",
                     help="skip the centralised IRLS Gauss-Newton leg on the same frames")
     ap.add_argument("--adjoint-frames", type=int, default=29,
@@ -577,6 +654,9 @@ def main():
         return
     if args.noise_sweep:
         noise_sweep()
+        return
+    if args.compare_solvers:
+        compare_solvers()
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (single-GPU build)", file=sys.stderr)

@@ -325,11 +325,11 @@ int pixvod_unroll_last_ms(const pixvod_unroll* u, double* forward_ms, double* ba
  * Centralised baseline: direct tracking with every pixel accessible at once
  * (Sec. 3.1, Eq. photo), solved by IRLS Gauss-Newton as the paper's
  * centralised comparison (Sec. 4.4). Unknowns: one global pose xi (right
- * perturbation) and a log-depth per keyframe pixel. The energy is the
- * per-pixel model's at exact consensus: photometric factors with the Huber
- * covariance weighting frozen at the current residuals, each pixel's pose and
- * log-depth prior, and the normal-integration factors; there are no identity
- * factors. Each IRLS iteration solves the Gauss-Newton normal equations
+ * perturbation) and a log-depth per keyframe pixel. The energy is Eq. (photo)
+ * with the per-pixel model's factors at exact consensus: photometric factors
+ * with the Huber covariance weighting frozen at the current residuals, each
+ * pixel's log-depth prior, the normal-integration factors and one prior
+ * factor on the pose; there are no identity factors. Each IRLS iteration solves the Gauss-Newton normal equations
  * (6 + H*W unknowns; the depth block is diagonal plus sigma_N^-2 times the
  * graph Laplacian of the active normal edges) by preconditioned conjugate
  * gradients in FP64 (block-Jacobi: the 6x6 pose block and the depth

@@ -6,12 +6,13 @@ checked against. It shares no code with the GPU library.
 
 One global relative pose xi (se(3), right perturbation T = Exp(xi) Exp(d))
 and a log-depth per keyframe pixel, with every measurement accessible at
-once. The energy is the per-pixel model's at exact consensus: every pixel's
-pose equals xi, so the identity factors vanish and each pixel keeps its
-photometric factor (Eq. distrb_photo, Huber by iteratively reweighted least
-squares: the weight kappa of the Huber covariance weighting at the current
-residual), its pose and log-depth prior (Eq. prior; N pose priors on the one
-pose) and the normal-integration factors (Eq. gbpni). One IRLS iteration
+once. The energy is Eq. (photo) with the per-pixel model's factors at exact
+consensus: every pixel's pose equals xi, so there are no identity factors;
+each pixel keeps its photometric factor (Eq. distrb_photo, Huber by
+iteratively reweighted least squares: the weight kappa of the Huber
+covariance weighting at the current residual), its log-depth prior and the
+normal-integration factors (Eq. gbpni); the one pose has one prior factor
+(Eq. prior) of the same strength. One IRLS iteration
 solves the Gauss-Newton normal equations of the model linearised at the
 current point, with the weights frozen there, exactly (sparse direct solve),
 and applies the step: xi <- Log(Exp(xi) Exp(d_xi)), ell <- ell + d_ell.
@@ -113,12 +114,12 @@ class Centralised:
         Jx, Jl = J[:, :6], J[:, 6]
         A = (Jx * w[:, None]).T @ Jx
         gx = -(Jx * (w * r)[:, None]).sum(0)
-        # N pose priors on the shared pose
+        # the prior factor of the one pose
         rp = log_se3(np.linalg.inv(exp_se3(self.prior_xi)) @ exp_se3(xi))
         Jp = prior_jac(rp)
-        A = A + N * self.lamP * Jp.T @ Jp
+        A = A + self.lamP * Jp.T @ Jp
         A = 0.5 * (A + A.T)          # symmetric by definition; drop the rounding asymmetry
-        gx = gx - N * self.lamP * Jp.T @ rp
+        gx = gx - self.lamP * Jp.T @ rp
         Bc = Jx * (w * Jl)[:, None]                             # (N, 6) coupling
         dg = w * Jl * Jl + self.lamP
         gl = -w * Jl * r - self.lamP * (ell - self.prior_ell)

@@ -3,14 +3,16 @@
 // log-depth per keyframe pixel, solved by IRLS Gauss-Newton with every pixel
 // accessible at once.
 //
-// The energy is the per-pixel model's at exact consensus (every pixel's pose
-// equal to the global one): photometric factors with the Huber covariance
-// weighting frozen at the current residuals, the pose and log-depth priors of
-// every pixel, and the normal-integration factors. Each IRLS iteration:
-//   1. linearises every pixel with the per-pixel model's unary factors at the
-//      shared pose (the pose block and gradient summed over pixels by a
-//      deterministic two-stage reduction, the pose-depth coupling and depth
-//      diagonal kept per pixel) and the normal-integration terms;
+// The energy is Eq. (photo) with the per-pixel model's factors at exact
+// consensus (every pixel's pose equal to the global one): photometric factors
+// with the Huber covariance weighting frozen at the current residuals, each
+// pixel's log-depth prior, the normal-integration factors, and one prior
+// factor on the pose. Each IRLS iteration:
+//   1. linearises every pixel's photometric factor with the per-pixel model's
+//      code at the shared pose (the pose block and gradient summed over pixels
+//      by a deterministic two-stage reduction, the pose-depth coupling and
+//      depth diagonal kept per pixel), its log-depth prior and the
+//      normal-integration terms; the pose prior is added once;
 //   2. solves the (6 + N) normal equations
 //        [A  B ] [d_xi ]   [g_xi ]
 //        [B' D ] [d_ell] = [g_ell],  D = diag + lamN * graph Laplacian,
@@ -122,6 +124,48 @@ __device__ inline void sym6_mul(const double A[21], const double x[6], double y[
     }
 }
 
+// pose prior (Eq. prior) at xi with precision lamP added to (A, g):
+// r = Log(Exp(xi_hat)^-1 Exp(xi)), J = I + ad(r)/2 + ad(r)^2/12
+__device__ inline void add_pose_prior(const Strengths& s, const double xi[6], double A[21], double g[6]) {
+    double R[9], t[3], rp[6];
+    se3_exp(xi, R, t);
+    if (s.prior_is_identity) {
+        for (int k = 0; k < 6; ++k) rp[k] = xi[k];
+    } else {
+        double Rr[9], tr[3];
+        se3_compose(s.prior_R, s.prior_t, R, t, Rr, tr);
+        se3_log(Rr, tr, rp);
+    }
+    double ad[36], J[36];
+    for (int k = 0; k < 36; ++k) ad[k] = 0.0;
+    const double* w = rp;
+    const double* p = rp + 3;
+    const double Wm[9] = {0.0, -w[2], w[1], w[2], 0.0, -w[0], -w[1], w[0], 0.0};
+    const double Pm[9] = {0.0, -p[2], p[1], p[2], 0.0, -p[0], -p[1], p[0], 0.0};
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            ad[r * 6 + c] = Wm[r * 3 + c];
+            ad[(r + 3) * 6 + c] = Pm[r * 3 + c];
+            ad[(r + 3) * 6 + c + 3] = Wm[r * 3 + c];
+        }
+    for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c) {
+            double a2 = 0.0;
+            for (int k = 0; k < 6; ++k) a2 += ad[r * 6 + k] * ad[k * 6 + c];
+            J[r * 6 + c] = (r == c ? 1.0 : 0.0) + 0.5 * ad[r * 6 + c] + a2 * (1.0 / 12.0);
+        }
+    for (int a = 0; a < 6; ++a) {
+        double e = 0.0;
+        for (int k = 0; k < 6; ++k) e += J[k * 6 + a] * rp[k];
+        g[a] -= s.lamP * e;
+        for (int b = a; b < 6; ++b) {
+            double m = 0.0;
+            for (int k = 0; k < 6; ++k) m += J[k * 6 + a] * J[k * 6 + b];
+            A[s6(a, b)] += s.lamP * m;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // kernels
 
@@ -157,8 +201,12 @@ __global__ __launch_bounds__(kThreads) void k_c_linearise(Geo g, Strengths s, In
         for (int k = 0; k < 6; ++k) tau[k] = cs->xi[k];
         se3_exp(tau, R, t);
         const double ell = P.ell[pi];
-        const bool val = unary_factors(g, s, in, u, v, tau, R, t, ell, L, eta);
-        double diag = L[s7(6, 6)], gl = eta[6];
+        // the photometric factor alone (zero prior weight); the log-depth prior
+        // is added here, the pose prior once per solve
+        Strengths sp = s;
+        sp.lamP = 0.0;
+        const bool val = unary_factors(g, sp, in, u, v, tau, R, t, ell, L, eta);
+        double diag = L[s7(6, 6)] + s.lamP, gl = eta[6] - s.lamP * (ell - s.prior_ell);
         if (s.lamN > 0.0) {
             for (int d = 0; d < 4; ++d) {
                 int nu, nv;
@@ -189,11 +237,14 @@ __global__ __launch_bounds__(kThreads) void k_c_linearise(Geo g, Strengths s, In
     block_reduce<kLinPartials>(red, partial);
 }
 
-__global__ __launch_bounds__(kThreads) void k_c_lin_final(int nb, const double* __restrict__ partial,
+__global__ __launch_bounds__(kThreads) void k_c_lin_final(Strengths s, int nb, const double* __restrict__ partial,
                                                           CgState* __restrict__ cs) {
     double tot[kLinPartials];
     final_sum<kLinPartials>(partial, nb, tot);
     if (threadIdx.x != 0) return;
+    double xi[6];
+    for (int k = 0; k < 6; ++k) xi[k] = cs->xi[k];
+    add_pose_prior(s, xi, tot, tot + 21);
     for (int k = 0; k < 21; ++k) cs->A[k] = tot[k];
     for (int k = 0; k < 6; ++k) {
         cs->g[k] = tot[21 + k];
@@ -371,6 +422,10 @@ struct pixvod_central {
     bool have_kf = false;
     double last_ms = 0.0;
     hipEvent_t ev[2] = {nullptr, nullptr};
+    // one IRLS iteration captured as a HIP graph on `graph_stream`
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t graph_stream = nullptr;
     std::string err;
 };
 
@@ -442,6 +497,8 @@ void crelease(pixvod_central* c) {
     if (c->h_cs) (void)hipHostFree(c->h_cs);
     for (hipEvent_t e : c->ev)
         if (e) (void)hipEventDestroy(e);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
 }
 
@@ -622,21 +679,51 @@ int pixvod_central_track(pixvod_central* c, const float* frame, int where, int n
     const Planes P = cplanes(c);
     const dim3 gr = cgrid(g), blk(64, 4);
     const double tol2 = c->tol * c->tol;
-    hipLaunchKernelGGL(k_c_reset_total, dim3(1), dim3(64), 0, c->stream, c->cs);
-    C_TRY(c, hipEventRecord(c->ev[0], c->stream));
-    for (int it = 0; it < n_iters; ++it) {
-        hipLaunchKernelGGL(k_c_linearise, gr, blk, 0, c->stream, g, s, in, c->cs, P, c->partial);
-        hipLaunchKernelGGL(k_c_lin_final, dim3(1), dim3(kThreads), 0, c->stream, c->nb, c->partial, c->cs);
+    // one IRLS iteration: linearise, max_cg CG iterations (the launches after
+    // convergence return at once), apply the step
+    auto irls_iteration = [&](hipStream_t st) {
+        hipLaunchKernelGGL(k_c_linearise, gr, blk, 0, st, g, s, in, c->cs, P, c->partial);
+        hipLaunchKernelGGL(k_c_lin_final, dim3(1), dim3(kThreads), 0, st, s, c->nb, c->partial, c->cs);
         for (int k = 0; k < c->max_cg; ++k) {
             const double* pin = (k & 1) ? P.p1 : P.p0;
             double* pout = (k & 1) ? P.p0 : P.p1;
-            hipLaunchKernelGGL(k_c_matvec, gr, blk, 0, c->stream, g, s, in, c->cs, P, pin, pout, c->partial);
-            hipLaunchKernelGGL(k_c_alpha, dim3(1), dim3(kThreads), 0, c->stream, c->nb, c->partial, c->cs);
-            hipLaunchKernelGGL(k_c_update, gr, blk, 0, c->stream, g, c->cs, P, pout, c->partial);
-            hipLaunchKernelGGL(k_c_beta, dim3(1), dim3(kThreads), 0, c->stream, c->nb, c->partial, c->cs, tol2);
+            hipLaunchKernelGGL(k_c_matvec, gr, blk, 0, st, g, s, in, c->cs, P, pin, pout, c->partial);
+            hipLaunchKernelGGL(k_c_alpha, dim3(1), dim3(kThreads), 0, st, c->nb, c->partial, c->cs);
+            hipLaunchKernelGGL(k_c_update, gr, blk, 0, st, g, c->cs, P, pout, c->partial);
+            hipLaunchKernelGGL(k_c_beta, dim3(1), dim3(kThreads), 0, st, c->nb, c->partial, c->cs, tol2);
         }
-        hipLaunchKernelGGL(k_c_apply, gr, blk, 0, c->stream, g, P);
-        hipLaunchKernelGGL(k_c_apply_pose, dim3(1), dim3(64), 0, c->stream, c->cs);
+        hipLaunchKernelGGL(k_c_apply, gr, blk, 0, st, g, P);
+        hipLaunchKernelGGL(k_c_apply_pose, dim3(1), dim3(64), 0, st, c->cs);
+    };
+    // captured once per stream as a graph (every argument is fixed for the
+    // solver's lifetime); plain launches if capture is unavailable
+    if (n_iters > 0 && c->graph_stream != c->stream) {
+        if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+        if (c->graph) (void)hipGraphDestroy(c->graph);
+        c->graph_exec = nullptr;
+        c->graph = nullptr;
+        c->graph_stream = nullptr;
+        if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            irls_iteration(c->stream);
+            hipGraph_t gph = nullptr;
+            if (hipStreamEndCapture(c->stream, &gph) == hipSuccess && gph) {
+                hipGraphExec_t ex = nullptr;
+                if (hipGraphInstantiate(&ex, gph, nullptr, nullptr, 0) == hipSuccess) {
+                    c->graph = gph;
+                    c->graph_exec = ex;
+                    c->graph_stream = c->stream;
+                } else {
+                    (void)hipGraphDestroy(gph);
+                }
+            }
+        }
+        (void)hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_c_reset_total, dim3(1), dim3(64), 0, c->stream, c->cs);
+    C_TRY(c, hipEventRecord(c->ev[0], c->stream));
+    for (int it = 0; it < n_iters; ++it) {
+        if (c->graph_exec) C_TRY(c, hipGraphLaunch(c->graph_exec, c->stream));
+        else irls_iteration(c->stream);
         C_TRY(c, hipGetLastError());
     }
     C_TRY(c, hipEventRecord(c->ev[1], c->stream));

@@ -77,6 +77,7 @@ def lib() -> C.CDLL:
         L.or_get_beliefs.argtypes = [C.c_void_p, dp, dp]
         L.or_get_normal_targets.argtypes = [C.c_void_p, dp, dp]
         L.or_get_gradients.argtypes = [C.c_void_p, dp, dp]
+        L.or_transfer_depth.argtypes = [C.c_void_p]
         L.or_tree_levels.restype = C.c_int
         L.or_tree_levels.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
         L.or_get_node_beliefs.argtypes = [C.c_void_p, dp, dp]
@@ -221,6 +222,13 @@ class Oracle:
         n = np.ascontiguousarray(normals, dtype=np.float32).reshape(self.N * 3)
         rc = lib().or_set_keyframe(self._h, _fp(i), _fp(n))
         assert rc == 0
+
+    def transfer_depth(self):
+        """Forward-warps the log-depths into the frame just tracked (call
+        before set_keyframe with that frame)."""
+        rc = lib().or_transfer_depth(self._h)
+        if rc != 0:
+            raise RuntimeError("depth transfer needs a tracked frame")
 
     def set_keyframe64(self, img, normals):
         i = np.ascontiguousarray(img, dtype=np.float64).reshape(self.N)

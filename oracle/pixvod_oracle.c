@@ -638,6 +638,41 @@ int or_set_keyframe64(or_ctx* x, const double* img, const float* normals) {
     return set_keyframe_impl(x, NULL, img, normals);
 }
 
+/* keyframe depth transfer (depth propagation, Sec. 3.3; re-anchoring, Sec.
+ * 3.5): the 3-D point exp(ell) q of every pixel of the current keyframe is
+ * moved into the camera of the frame just tracked by that frame's pose
+ * estimate Exp(xi) (keyframe points to current camera) and splatted to the
+ * nearest pixel of the new keyframe (rounding half up); where several land,
+ * the nearest depth (compared at FP32) wins; pixels nothing lands on keep
+ * their log-depth. The new log-depth is log of the point's depth z. */
+int or_transfer_depth(or_ctx* x) {
+    if (!x || !x->have_track) return -2;
+    const or_config* c = &x->cfg;
+    const int W = c->W, H = c->H, N = x->N;
+    double T[16];
+    or_se3_exp(x->xi_last, T);
+    float* zb = (float*)malloc(sizeof(float) * (size_t)N);
+    for (int j = 0; j < N; ++j) zb[j] = INFINITY;
+    for (int i = 0; i < N; ++i) {
+        const int u = i % W, v = i / W;
+        const double d = exp(x->ell[i]);
+        const double P[3] = {d * (u - c->cx) / c->fx, d * (v - c->cy) / c->fy, d};
+        double Q[3];
+        for (int r = 0; r < 3; ++r) Q[r] = T[r * 4] * P[0] + T[r * 4 + 1] * P[1] + T[r * 4 + 2] * P[2] + T[r * 4 + 3];
+        if (!(Q[2] > 0.0)) continue;
+        const double uu = c->fx * Q[0] / Q[2] + c->cx, vv = c->fy * Q[1] / Q[2] + c->cy;
+        const double ju = floor(uu + 0.5), jv = floor(vv + 0.5);
+        if (!(ju >= 0.0 && ju < (double)W && jv >= 0.0 && jv < (double)H)) continue;
+        const int j = (int)jv * W + (int)ju;
+        const float z = (float)Q[2];
+        if (z < zb[j]) zb[j] = z;
+    }
+    for (int j = 0; j < N; ++j)
+        if (zb[j] < INFINITY) x->ell[j] = log((double)zb[j]);
+    free(zb);
+    return 0;
+}
+
 static void set_frame_impl(or_ctx* x, const float* f32, const double* f64) {
     const int H = x->cfg.H, W = x->cfg.W;
     for (int i = 0; i < x->N; ++i) x->I_t[i] = f64 ? f64[i] : (double)f32[i];

@@ -99,6 +99,13 @@ int or_set_keyframe(or_ctx* ctx, const float* img, const float* normals);
 int or_track(or_ctx* ctx, const float* frame, int n_iters, or_track_out* out,
              double* inv_depth, double* inv_depth_var);
 
+/* keyframe depth transfer before re-anchoring on the frame just tracked: the
+ * log-depths of the current keyframe are forward-warped into that frame with
+ * its pose estimate (nearest-pixel splat, nearest depth wins, pixels nothing
+ * lands on keep theirs); then call or_set_keyframe with the new keyframe.
+ * -2 before a tracked frame. */
+int or_transfer_depth(or_ctx* ctx);
+
 /* double-precision image variants (exact synthetic constructions in tests) */
 int or_set_keyframe64(or_ctx* ctx, const double* img, const float* normals);
 int or_set_frame64(or_ctx* ctx, const double* frame);

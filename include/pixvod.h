@@ -164,6 +164,16 @@ int pixvod_tree_levels(const pixvod_ctx* ctx, int* n_levels, int* hw);
  * pose (re-anchoring on the frame just tracked). */
 int pixvod_set_keyframe(pixvod_ctx* ctx, const float* img, const float* normals, int where);
 
+/* Re-anchoring with depth transfer (depth propagation, Sec. 3.3): as
+ * pixvod_set_keyframe, but first the current log-depths are forward-warped
+ * into the frame just tracked, which `img` should be: each keyframe pixel's
+ * 3-D point exp(log depth) q is moved by the last pose estimate
+ * (Eq. estimator_avg) and splatted to the nearest pixel (rounding half up);
+ * the nearest depth (compared at FP32) wins, and pixels no point lands on keep
+ * their log-depth. One extra H x W plane is allocated on first use.
+ * PIXVOD_ESTATE before a tracked frame. */
+int pixvod_set_keyframe_transfer(pixvod_ctx* ctx, const float* img, const float* normals, int where);
+
 /* Optional per-pixel photometric sigma map (H*W); NULL restores the constant
  * params.sigma_D. */
 int pixvod_set_sigma_map(pixvod_ctx* ctx, const float* sigma_D_map, int where);

@@ -77,6 +77,7 @@ _SIGNATURES = {
     "pixvod_tree_levels": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "pixvod_set_keyframe": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "pixvod_set_sigma_map": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "pixvod_set_keyframe_transfer": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "pixvod_track": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.POINTER(TrackOut)]),
     "pixvod_iterate": (C.c_int, [C.c_void_p, C.c_int]),
     "pixvod_set_prior": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
@@ -205,12 +206,15 @@ class Tracker:
     def set_schedule(self, schedule: int):
         _check(lib().pixvod_set_schedule(self._h, int(schedule)), self._h)
 
-    def set_keyframe(self, img, normals):
+    def set_keyframe(self, img, normals, transfer_depth: bool = False):
+        """New keyframe; with transfer_depth the log-depths are first
+        forward-warped into it (img should be the frame just tracked)."""
         pi, wi, ki = _ptr(img)
         pn, wn, kn = _ptr(normals)
         if wi != wn:
             raise ValueError("image and normals must live in the same memory")
-        _check(lib().pixvod_set_keyframe(self._h, C.c_void_p(pi), C.c_void_p(pn), wi), self._h)
+        f = lib().pixvod_set_keyframe_transfer if transfer_depth else lib().pixvod_set_keyframe
+        _check(f(self._h, C.c_void_p(pi), C.c_void_p(pn), wi), self._h)
 
     def set_sigma_map(self, sigma):
         if sigma is None:

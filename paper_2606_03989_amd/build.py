@@ -15,7 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpixvod.so")
-SOURCES = ["gbp_kernels.hip", "gbp_adjoint.hip", "gbp_tree.hip", "pixvod_runtime.hip", "pixvod_unroll.hip", "pixvod_central.hip"]
+SOURCES = ["gbp_kernels.hip", "gbp_adjoint.hip", "gbp_tree.hip", "gbp_transfer.hip", "pixvod_runtime.hip", "pixvod_unroll.hip", "pixvod_central.hip"]
 ARCH = os.environ.get("PIXVOD_ARCH", "gfx950")
 
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -16,6 +16,7 @@
 #include "../../include/pixvod.h"
 #include "gbp_device.hpp"
 #include "gbp_kernels.h"
+#include "gbp_transfer.h"
 #include "gbp_tree.h"
 #include "runtime_internal.h"
 
@@ -44,6 +45,7 @@ struct pixvod_ctx {
     float *var_ll = nullptr, *valid = nullptr;
     float *frame_stage = nullptr, *kf_stage = nullptr, *out_stage = nullptr;
     float* dense_state = nullptr;
+    unsigned* zbuf = nullptr;            // depth-transfer z-buffer (allocated on first use)
     double* marg = nullptr;
     double* msg = nullptr;
     double *partial = nullptr, *result = nullptr;
@@ -277,7 +279,7 @@ static void prof_collect(pixvod_ctx* c) {
 
 static void release(pixvod_ctx* c) {
     void* bufs[] = {c->X[0], c->X[1], c->NX[0], c->NX[1], c->Is, c->cxt, c->cyt, c->sig, c->It, c->Gx, c->Gy, c->prior_ell, c->var_ll,
-                    c->valid, c->frame_stage, c->kf_stage, c->out_stage, c->dense_state, c->marg, c->msg,
+                    c->valid, c->frame_stage, c->kf_stage, c->out_stage, c->dense_state, c->zbuf, c->marg, c->msg,
                     c->partial, c->result, c->health};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -510,6 +512,26 @@ int pixvod_set_keyframe(pixvod_ctx* c, const float* img, const float* normals, i
     c->frames_since_kf = 0;
     if (where == PIXVOD_HOST) HIP_TRY(c, hipStreamSynchronize(c->stream));
     return PIXVOD_OK;
+}
+
+int pixvod_set_keyframe_transfer(pixvod_ctx* c, const float* img, const float* normals, int where) {
+    if (!c) return fail(nullptr, PIXVOD_EINVAL, "ctx is NULL");
+    if (!img || !normals) return fail(c, PIXVOD_EINVAL, "img and normals are required");
+    if (where != PIXVOD_HOST && where != PIXVOD_DEVICE) return fail(c, PIXVOD_EINVAL, "bad location");
+    if (!c->have_track) return fail(c, PIXVOD_ESTATE, "no tracked frame since the keyframe");
+    if (!c->zbuf) {
+        int rc = dev_alloc(c, &c->zbuf, (size_t)c->plane);
+        if (rc) return rc;
+    }
+    double T[16];
+    host_se3_exp(c->xi_last, T);
+    Pose p;
+    for (int r = 0; r < 3; ++r) {
+        for (int k = 0; k < 3; ++k) p.R[r * 3 + k] = T[r * 4 + k];
+        p.t[r] = T[r * 4 + 3];
+    }
+    HIP_TRY(c, launch_depth_transfer(geo_of(c), p, c->X[c->cur], c->zbuf, c->stream));
+    return pixvod_set_keyframe(c, img, normals, where);
 }
 
 int pixvod_set_sigma_map(pixvod_ctx* c, const float* map, int where) {

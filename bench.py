@@ -34,11 +34,14 @@ STATE_PLANES = 123
 BYTES_PER_PX_ITER = STATE_PLANES * 4 * 2 + 4 + 8 + 12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fused_iterate_vga.json")
 KERNEL_SOURCES = ["paper_2606_03989_amd/csrc/gbp_kernels.hip", "paper_2606_03989_amd/csrc/gbp_device.hpp"]
+TREE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_quadtree_iterate_vga.json")
+TREE_KERNEL_SOURCES = ["paper_2606_03989_amd/csrc/gbp_tree.hip", "paper_2606_03989_amd/csrc/gbp_tree.h",
+                       "paper_2606_03989_amd/csrc/gbp_device.hpp"]
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -217,10 +220,16 @@ def run_quadtree(args, g):
     achieved = bytes_per_pass / pass_s / 1e9
     log(f"quadtree: {value:.1f} Mpx-iter/s, pass {pass_s * 1e6:.1f} us ({levels} levels, {n_nodes} nodes), "
         f"{achieved:.0f} GB/s algorithmic; flags seen {flags}")
+    traffic = None
+    if os.path.exists(TREE_TRAFFIC_FILE):
+        with open(TREE_TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_source_hash") == kernel_source_hash(TREE_KERNEL_SOURCES):
+            traffic = tr.get("bytes_per_pass")
     return dict(value=round(value, 1), unit="Mpixel-iter/s", levels=levels, nodes=n_nodes,
                 pass_us=round(pass_s * 1e6, 2), grid_pass_us=round(g["pass_us"], 2),
                 pass_speedup_vs_grid=round(g["pass_us"] / (pass_s * 1e6), 3),
-                bytes_per_pass=int(bytes_per_pass), achieved_GBs=round(achieved, 1),
+                bytes_per_pass=int(bytes_per_pass), traffic=traffic, achieved_GBs=round(achieved, 1),
                 frac=round(achieved / HBM_PEAK_GBS, 4), vs_grid=round(value / g["value"], 3))
 
 
@@ -585,6 +594,14 @@ def probe(frames: int = 3, copy_mb: int = 512):
         for f in (d_fr if sched == pv.SCHED_FUSED else d_fr[:1]):
             t.track(f, 20, maps=False)
         t.close()
+    # the quadtree topology on the same frames
+    t = pv.Tracker(cam.H, cam.W, (cam.fx, cam.fy, cam.cx, cam.cy), **VGA_PARAMS)
+    t.set_stream(torch.cuda.current_stream())
+    t.set_topology(pv.TOPO_QUADTREE)
+    t.set_keyframe(torch.from_numpy(I0).to(dev), torch.from_numpy(N0).to(dev))
+    for f in d_fr:
+        t.track(f, 20, maps=False)
+    t.close()
     # calibration: a plain device copy of a source evicted from the last-level
     # cache by a larger fill in between, so every source byte comes from HBM
     n = copy_mb * (1 << 20) // 4

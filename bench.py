@@ -561,6 +561,68 @@ def compare_solvers(n_frames: int = 10):
                       "sigma_P 0.01, Huber k 400; centralised CG tolerance 1e-8"}))
 
 
+def transfer_check(every: int = 5, n_frames: int = 20, iters: int = 20):
+    """Re-anchoring with and without keyframe depth transfer (depth propagation,
+    Sec. 3.3) on the 256x256 slow-motion scene: a new keyframe every `every`
+    frames; after each re-anchoring, the inverse-depth error of the carried
+    state against the rendered depth of the new keyframe, before any iteration
+    on it and after the next frame. Also the duration of the transfer at
+    640x480. Prints one JSON line."""
+    import dataclasses
+    import numpy as np
+    import torch
+    import paper_2606_03989_amd as pv
+    from synth.scenes import SEQUENCE_CONFIGS, make_sequence_scene, render, sequence_poses
+    cfg = dataclasses.replace(SEQUENCE_CONFIGS["ppa256"], max_step_t=0.002, max_step_r_deg=0.1, noise_sigma=0.0)
+    scene, cam = make_sequence_scene(cfg)
+    poses = sequence_poses(cfg)
+    K = (cam.fx, cam.fy, cam.cx, cam.cy)
+    frames = [render(scene, cam, poses[f]) for f in range(n_frames + 1)]
+    out = {}
+    for transfer in (False, True):
+        t = pv.Tracker(cam.H, cam.W, K, sigma_P=0.01, huber_k=400.0)
+        t.set_keyframe(np.ascontiguousarray(frames[0][0], np.float32), np.ascontiguousarray(frames[0][2], np.float32))
+        before, after = [], []
+        pending = None
+        for f in range(1, n_frames + 1):
+            img = np.ascontiguousarray(frames[f][0], np.float32)
+            r = t.track(img, iters)
+            if pending is not None:
+                after.append(float(np.median(np.abs(r["inv_depth"] - pending) / pending)))
+                pending = None
+            if f % every == 0 and f < n_frames:
+                t.set_keyframe(img, np.ascontiguousarray(frames[f][2], np.float32), transfer_depth=transfer)
+                st = t.get_state()
+                rho_true = 1.0 / frames[f][1]
+                rho = np.exp(-st[6].astype(np.float64))
+                before.append(float(np.median(np.abs(rho - rho_true) / rho_true)))
+                pending = rho_true
+        t.close()
+        key = "transfer" if transfer else "carry_over"
+        out[key] = dict(median_inv_depth_err_at_reanchor=round(float(np.mean(before)), 4),
+                        median_inv_depth_err_after_next_frame=round(float(np.mean(after)), 4))
+        log(f"{key}: {out[key]}")
+    # duration of one transfer at 640x480
+    cam2, I0, N0, fr, nr = vga_inputs(2)
+    dev = torch.device("cuda:0")
+    t = pv.Tracker(cam2.H, cam2.W, (cam2.fx, cam2.fy, cam2.cx, cam2.cy), **VGA_PARAMS)
+    t.set_keyframe(torch.from_numpy(I0).to(dev), torch.from_numpy(N0).to(dev))
+    d0, n0 = torch.from_numpy(fr[0]).to(dev), torch.from_numpy(nr[0]).to(dev)
+    t.track(d0, 5, maps=False)
+    ms = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        t.set_keyframe(d0, n0, transfer_depth=True)
+        torch.cuda.synchronize()
+        ms.append((time.perf_counter() - a) * 1e3)
+        t.track(d0, 1, maps=False)
+    t.close()
+    out["reanchor_with_transfer_ms_640x480"] = round(float(np.median(ms)), 3)
+    print(json.dumps({"depth_transfer": out, "workload": f"256x256 six-plane scene, slow motion, keyframe every {every} "
+                      f"frames, frames 1-{n_frames}, {iters} iterations; timing at 640x480"}))
+
+
 def pv_exp(xi):
     """Exp of Eq. (exp_err) as a 4x4 matrix (reporting only)."""
     import numpy as np
@@ -659,6 +721,8 @@ def main():
     ap.add_argument("--batch-seqs", type=int, default=64)
     ap.add_argument("--no-quadtree", dest="quadtree", action="store_false",
                     help="skip the quadtree-topology leg on the same frames")
+    ap.add_argument("--transfer-check", action="store_true",
+                    help="re-anchoring with and without keyframe depth transfer; its own JSON line")
     ap.add_argument("--compare-solvers", action="store_true",
                     help="centralised IRLS against distributed GBP on the slow-motion 256x256 scene; its own JSON line")
     ap.add_argument("--no-central", dest="central", action="store_false",
@@ -674,6 +738,9 @@ def main():
         return
     if args.compare_solvers:
         compare_solvers()
+        return
+    if args.transfer_check:
+        transfer_check()
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (single-GPU build)", file=sys.stderr)

@@ -53,48 +53,54 @@ def lib() -> C.CDLL:
         if not os.path.exists(LIB_PATH):
             from . import build as _b
             _b.build()
-        L = C.CDLL(LIB_PATH)
-        dp = C.POINTER(C.c_double)
-        fp = C.POINTER(C.c_float)
-        L.or_create.restype = C.c_void_p
-        L.or_create.argtypes = [C.POINTER(OrConfig)]
-        L.or_destroy.argtypes = [C.c_void_p]
-        L.or_default_config.argtypes = [C.POINTER(OrConfig)]
-        L.or_set_sigma_D_map.argtypes = [C.c_void_p, dp]
-        L.or_set_prior.argtypes = [C.c_void_p, dp, dp]
-        L.or_set_prior_from_state.argtypes = [C.c_void_p]
-        L.or_set_keyframe.argtypes = [C.c_void_p, fp, fp]
-        L.or_track.argtypes = [C.c_void_p, fp, C.c_int, C.POINTER(OrTrackOut), dp, dp]
-        L.or_iterate.argtypes = [C.c_void_p, C.c_int]
-        L.or_set_keyframe64.argtypes = [C.c_void_p, dp, fp]
-        L.or_set_frame64.argtypes = [C.c_void_p, dp]
-        L.or_set_frame.argtypes = [C.c_void_p, fp]
-        L.or_state_doubles.restype = C.c_size_t
-        L.or_state_doubles.argtypes = [C.c_void_p]
-        L.or_get_state.argtypes = [C.c_void_p, dp]
-        L.or_set_state.argtypes = [C.c_void_p, dp]
-        L.or_get_means.argtypes = [C.c_void_p, dp]
-        L.or_get_beliefs.argtypes = [C.c_void_p, dp, dp]
-        L.or_get_normal_targets.argtypes = [C.c_void_p, dp, dp]
-        L.or_get_gradients.argtypes = [C.c_void_p, dp, dp]
-        L.or_transfer_depth.argtypes = [C.c_void_p]
-        L.or_tree_levels.restype = C.c_int
-        L.or_tree_levels.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
-        L.or_get_node_beliefs.argtypes = [C.c_void_p, dp, dp]
-        L.or_energy.restype = C.c_double
-        L.or_energy.argtypes = [C.c_void_p]
-        L.or_se3_exp.argtypes = [dp, dp]
-        L.or_se3_log.argtypes = [dp, dp]
-        L.or_se3_jr.argtypes = [dp, dp]
-        L.or_prior_jacobian.argtypes = [dp, dp]
-        L.or_huber_weight.restype = C.c_double
-        L.or_huber_weight.argtypes = [C.c_double, C.c_double]
-        L.or_warp.argtypes = [C.c_void_p, C.c_double, C.c_double, dp, C.c_double, dp, dp]
-        L.or_unary.argtypes = [C.c_void_p, C.c_int, C.c_int, dp, dp, C.POINTER(C.c_int)]
-        L.or_factor_message.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, dp]
-        L.or_threads.restype = C.c_int
-        _lib = L
+        _lib = load(LIB_PATH)
     return _lib
+
+
+def load(path: str) -> C.CDLL:
+    """Loads an oracle library built from pixvod_oracle.c (the oracle itself, or
+    a variant the tests build with a planted fault) and declares its calls."""
+    L = C.CDLL(path)
+    dp = C.POINTER(C.c_double)
+    fp = C.POINTER(C.c_float)
+    L.or_create.restype = C.c_void_p
+    L.or_create.argtypes = [C.POINTER(OrConfig)]
+    L.or_destroy.argtypes = [C.c_void_p]
+    L.or_default_config.argtypes = [C.POINTER(OrConfig)]
+    L.or_set_sigma_D_map.argtypes = [C.c_void_p, dp]
+    L.or_set_prior.argtypes = [C.c_void_p, dp, dp]
+    L.or_set_prior_from_state.argtypes = [C.c_void_p]
+    L.or_set_keyframe.argtypes = [C.c_void_p, fp, fp]
+    L.or_track.argtypes = [C.c_void_p, fp, C.c_int, C.POINTER(OrTrackOut), dp, dp]
+    L.or_iterate.argtypes = [C.c_void_p, C.c_int]
+    L.or_set_keyframe64.argtypes = [C.c_void_p, dp, fp]
+    L.or_set_frame64.argtypes = [C.c_void_p, dp]
+    L.or_set_frame.argtypes = [C.c_void_p, fp]
+    L.or_state_doubles.restype = C.c_size_t
+    L.or_state_doubles.argtypes = [C.c_void_p]
+    L.or_get_state.argtypes = [C.c_void_p, dp]
+    L.or_set_state.argtypes = [C.c_void_p, dp]
+    L.or_get_means.argtypes = [C.c_void_p, dp]
+    L.or_get_beliefs.argtypes = [C.c_void_p, dp, dp]
+    L.or_get_normal_targets.argtypes = [C.c_void_p, dp, dp]
+    L.or_get_gradients.argtypes = [C.c_void_p, dp, dp]
+    L.or_transfer_depth.argtypes = [C.c_void_p]
+    L.or_tree_levels.restype = C.c_int
+    L.or_tree_levels.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
+    L.or_get_node_beliefs.argtypes = [C.c_void_p, dp, dp]
+    L.or_energy.restype = C.c_double
+    L.or_energy.argtypes = [C.c_void_p]
+    L.or_se3_exp.argtypes = [dp, dp]
+    L.or_se3_log.argtypes = [dp, dp]
+    L.or_se3_jr.argtypes = [dp, dp]
+    L.or_prior_jacobian.argtypes = [dp, dp]
+    L.or_huber_weight.restype = C.c_double
+    L.or_huber_weight.argtypes = [C.c_double, C.c_double]
+    L.or_warp.argtypes = [C.c_void_p, C.c_double, C.c_double, dp, C.c_double, dp, dp]
+    L.or_unary.argtypes = [C.c_void_p, C.c_int, C.c_int, dp, dp, C.POINTER(C.c_int)]
+    L.or_factor_message.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, dp]
+    L.or_threads.restype = C.c_int
+    return L
 
 
 def _dp(a: np.ndarray):
@@ -178,16 +184,17 @@ def factor_message(r, J, prec, eta_s, lam_s):
 class Oracle:
     """One oracle context: keyframe, target frames, GBP state (FP64)."""
 
-    def __init__(self, cfg: OrConfig):
+    def __init__(self, cfg: OrConfig, library: Optional[C.CDLL] = None):
         self.cfg = cfg
         self.H, self.W = cfg.H, cfg.W
-        self._h = lib().or_create(C.byref(cfg))
+        self._L = library if library is not None else lib()
+        self._h = self._L.or_create(C.byref(cfg))
         if not self._h:
             raise ValueError("invalid oracle configuration")
 
     def close(self):
         if self._h:
-            lib().or_destroy(self._h)
+            self._L.or_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -202,56 +209,56 @@ class Oracle:
 
     def set_sigma_D_map(self, sig: Optional[np.ndarray]):
         if sig is None:
-            lib().or_set_sigma_D_map(self._h, None)
+            self._L.or_set_sigma_D_map(self._h, None)
         else:
             s = np.ascontiguousarray(sig, dtype=np.float64).reshape(self.N)
-            lib().or_set_sigma_D_map(self._h, _dp(s))
+            self._L.or_set_sigma_D_map(self._h, _dp(s))
 
     def set_prior(self, xi=None, log_depth=None):
         """Prior means: pose xi (6) and per-pixel log-depths (H x W); None keeps them."""
         x = None if xi is None else np.ascontiguousarray(xi, dtype=np.float64)
         d = None if log_depth is None else np.ascontiguousarray(log_depth, dtype=np.float64).reshape(self.N)
-        lib().or_set_prior(self._h, None if x is None else _dp(x), None if d is None else _dp(d))
+        self._L.or_set_prior(self._h, None if x is None else _dp(x), None if d is None else _dp(d))
 
     def set_prior_from_state(self):
         """Temporal priors: the current mean pose and log-depths become the prior means."""
-        lib().or_set_prior_from_state(self._h)
+        self._L.or_set_prior_from_state(self._h)
 
     def set_keyframe(self, img, normals):
         i = np.ascontiguousarray(img, dtype=np.float32).reshape(self.N)
         n = np.ascontiguousarray(normals, dtype=np.float32).reshape(self.N * 3)
-        rc = lib().or_set_keyframe(self._h, _fp(i), _fp(n))
+        rc = self._L.or_set_keyframe(self._h, _fp(i), _fp(n))
         assert rc == 0
 
     def transfer_depth(self):
         """Forward-warps the log-depths into the frame just tracked (call
         before set_keyframe with that frame)."""
-        rc = lib().or_transfer_depth(self._h)
+        rc = self._L.or_transfer_depth(self._h)
         if rc != 0:
             raise RuntimeError("depth transfer needs a tracked frame")
 
     def set_keyframe64(self, img, normals):
         i = np.ascontiguousarray(img, dtype=np.float64).reshape(self.N)
         n = np.ascontiguousarray(normals, dtype=np.float32).reshape(self.N * 3)
-        assert lib().or_set_keyframe64(self._h, _dp(i), _fp(n)) == 0
+        assert self._L.or_set_keyframe64(self._h, _dp(i), _fp(n)) == 0
 
     def set_frame64(self, frame):
         f = np.ascontiguousarray(frame, dtype=np.float64).reshape(self.N)
-        lib().or_set_frame64(self._h, _dp(f))
+        self._L.or_set_frame64(self._h, _dp(f))
 
     def set_frame(self, frame):
         f = np.ascontiguousarray(frame, dtype=np.float32).reshape(self.N)
-        lib().or_set_frame(self._h, _fp(f))
+        self._L.or_set_frame(self._h, _fp(f))
 
     def iterate(self, n: int) -> int:
-        return lib().or_iterate(self._h, int(n))
+        return self._L.or_iterate(self._h, int(n))
 
     def track(self, frame, n_iters: int):
         f = np.ascontiguousarray(frame, dtype=np.float32).reshape(self.N)
         out = OrTrackOut()
         inv = np.zeros(self.N)
         var = np.zeros(self.N)
-        rc = lib().or_track(self._h, _fp(f), int(n_iters), C.byref(out), _dp(inv), _dp(var))
+        rc = self._L.or_track(self._h, _fp(f), int(n_iters), C.byref(out), _dp(inv), _dp(var))
         if rc != 0:
             raise RuntimeError(f"or_track failed: {rc}")
         return dict(xi=np.array(out.xi[:]), T_world=np.array(out.T_world[:]).reshape(4, 4),
@@ -266,7 +273,7 @@ class Oracle:
     def tree_levels(self):
         """[(rows, cols)] of levels 0 (pixels) .. L (root); [(H, W)] for the grid."""
         hw = (C.c_int * 64)()
-        L = lib().or_tree_levels(self._h, hw)
+        L = self._L.or_tree_levels(self._h, hw)
         return [(hw[2 * l], hw[2 * l + 1]) for l in range(L + 1)]
 
     @property
@@ -275,9 +282,9 @@ class Oracle:
 
     def get_state(self):
         """Grid: (H, W, 123). Quadtree: ((H, W, 42) pixel part, (n_nodes, 141) node part)."""
-        n = lib().or_state_doubles(self._h)
+        n = self._L.or_state_doubles(self._h)
         s = np.zeros(n)
-        lib().or_get_state(self._h, _dp(s))
+        self._L.or_get_state(self._h, _dp(s))
         if not self.tree:
             return s.reshape(self.H, self.W, 123)
         return s[:self.N * 42].reshape(self.H, self.W, 42), s[self.N * 42:].reshape(-1, 141)
@@ -288,50 +295,50 @@ class Oracle:
             s = np.concatenate([np.asarray(pix, dtype=np.float64).reshape(-1),
                                 np.asarray(nodes, dtype=np.float64).reshape(-1)])
         s = np.ascontiguousarray(s, dtype=np.float64).reshape(-1)
-        assert s.size == lib().or_state_doubles(self._h)
-        lib().or_set_state(self._h, _dp(s))
+        assert s.size == self._L.or_state_doubles(self._h)
+        self._L.or_set_state(self._h, _dp(s))
 
     def node_beliefs(self):
         n = self.n_nodes
         lam = np.zeros(n * 49)
         eta = np.zeros(n * 7)
-        lib().or_get_node_beliefs(self._h, _dp(lam), _dp(eta))
+        self._L.or_get_node_beliefs(self._h, _dp(lam), _dp(eta))
         return lam.reshape(n, 7, 7), eta.reshape(n, 7)
 
     def means(self) -> np.ndarray:
         m = np.zeros(self.N * 7)
-        lib().or_get_means(self._h, _dp(m))
+        self._L.or_get_means(self._h, _dp(m))
         return m.reshape(self.H, self.W, 7)
 
     def beliefs(self):
         lam = np.zeros(self.N * 49)
         eta = np.zeros(self.N * 7)
-        lib().or_get_beliefs(self._h, _dp(lam), _dp(eta))
+        self._L.or_get_beliefs(self._h, _dp(lam), _dp(eta))
         return lam.reshape(self.H, self.W, 7, 7), eta.reshape(self.H, self.W, 7)
 
     def normal_targets(self):
         cx, cy = np.zeros(self.N), np.zeros(self.N)
-        lib().or_get_normal_targets(self._h, _dp(cx), _dp(cy))
+        self._L.or_get_normal_targets(self._h, _dp(cx), _dp(cy))
         return cx.reshape(self.H, self.W), cy.reshape(self.H, self.W)
 
     def gradients(self):
         gx, gy = np.zeros(self.N), np.zeros(self.N)
-        lib().or_get_gradients(self._h, _dp(gx), _dp(gy))
+        self._L.or_get_gradients(self._h, _dp(gx), _dp(gy))
         return gx.reshape(self.H, self.W), gy.reshape(self.H, self.W)
 
     def energy(self) -> float:
-        return lib().or_energy(self._h)
+        return self._L.or_energy(self._h)
 
     def warp(self, u: float, v: float, tau, ell: float):
         t = np.ascontiguousarray(tau, dtype=np.float64)
         w, J = np.zeros(2), np.zeros(14)
-        ok = lib().or_warp(self._h, float(u), float(v), _dp(t), float(ell), _dp(w), _dp(J))
+        ok = self._L.or_warp(self._h, float(u), float(v), _dp(t), float(ell), _dp(w), _dp(J))
         return bool(ok), w, J.reshape(2, 7)
 
     def unary(self, u: int, v: int):
         eta, lam = np.zeros(7), np.zeros(49)
         valid = C.c_int(0)
-        rc = lib().or_unary(self._h, int(u), int(v), _dp(eta), _dp(lam), C.byref(valid))
+        rc = self._L.or_unary(self._h, int(u), int(v), _dp(eta), _dp(lam), C.byref(valid))
         assert rc == 0
         return eta, lam.reshape(7, 7), bool(valid.value)
 

@@ -767,6 +767,14 @@ static void g7_damp(g7* nm, const g7* om, double bta) {
     for (int a = 0; a < 49; ++a) nm->lam[a] = (1.0 - bta) * nm->lam[a] + bta * om->lam[a];
 }
 
+/* Planted faults for the test-suite's check that the transport pins can fail
+ * (the oracle's own build never defines OR_PLANTED_FAULT): 1 drops the
+ * transport, 2 transports the identity-factor slots only, 3 transports with
+ * the information of the message that was replaced. */
+#ifndef OR_PLANTED_FAULT
+#define OR_PLANTED_FAULT 0
+#endif
+
 /* first-order transport of a stored message into the tangent space moved by m */
 static void g7_transport(g7* g, const double m[7]) {
     for (int a = 0; a < 7; ++a) {
@@ -911,6 +919,10 @@ static int iterate_once(or_ctx* x) {
 #pragma omp parallel for schedule(static) reduction(| : fail)
     for (int i = 0; i < N; ++i) {
         g7* mi = &x->msg[8 * (size_t)i];
+#if OR_PLANTED_FAULT == 3
+        g7 replaced[8];
+        memcpy(replaced, mi, 8 * sizeof(g7));
+#endif
         memcpy(mi, &x->newmsg[8 * (size_t)i], 8 * sizeof(g7));
         g7 b = x->unary[i];
         for (int k = 0; k < 8; ++k) g7_add(&b, &mi[k]);
@@ -942,7 +954,18 @@ static int iterate_once(or_ctx* x) {
         or_se3_log(T1, ti);
         x->ell[i] += m[6];
         /* first-order transport of stored messages into the new tangent space */
+#if OR_PLANTED_FAULT == 0
         for (int k = 0; k < 8; ++k) g7_transport(&mi[k], m);
+#elif OR_PLANTED_FAULT == 2
+        for (int k = 0; k < 4; ++k) g7_transport(&mi[k], m);
+#elif OR_PLANTED_FAULT == 3
+        for (int k = 0; k < 8; ++k) {
+            g7 t = replaced[k];
+            memcpy(t.eta, mi[k].eta, sizeof(t.eta));
+            g7_transport(&t, m);
+            memcpy(mi[k].eta, t.eta, sizeof(t.eta));
+        }
+#endif
         if (tree) g7_transport(&x->pmsg[i], m);
     }
 #pragma omp parallel for schedule(static) reduction(| : fail)

@@ -272,8 +272,11 @@ int pixvod_batch_autotune(pixvod_batch* b, int n_iters, int* tile_x, int* tile_y
 /* Average duration (ms) of the last frame step, timed with HIP events. */
 int pixvod_batch_last_step_ms(pixvod_batch* b, double* ms);
 
-/* Per-sequence state in the exchange layout of pixvod_get_state. */
+/* Per-sequence state in the exchange layout of pixvod_get_state; set_state
+ * replaces sequence seq's canonical state (its keyframe and frame counter are
+ * kept). */
 int pixvod_batch_get_state(pixvod_batch* b, int seq, void* dst, int where);
+int pixvod_batch_set_state(pixvod_batch* b, int seq, const void* src, int where);
 
 /* ---------------------------------------------------------------------------
  * Differentiation: unrolled tracking with a hand-written adjoint.

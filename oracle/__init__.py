@@ -30,6 +30,7 @@ class OrConfig(C.Structure):
         ("damping", C.c_double),
         ("frozen", C.c_int), ("full_jacobian", C.c_int),
         ("topology", C.c_int),
+        ("store_fp32", C.c_int),
     ]
 
 

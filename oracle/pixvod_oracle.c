@@ -784,6 +784,14 @@ static void g7_transport(g7* g, const double m[7]) {
     }
 }
 
+/* storage emulation (test switch): FP32 rounding of a message */
+static void g7_round32(g7* g) {
+    for (int a = 0; a < 7; ++a) g->eta[a] = (double)(float)g->eta[a];
+    for (int a = 0; a < 49; ++a) g->lam[a] = (double)(float)g->lam[a];
+}
+
+static double round32(double x) { return (double)(float)x; }
+
 /* quadtree node helpers */
 static int node_level(const or_ctx* x, int n) {
     int l = 1;
@@ -915,6 +923,17 @@ static int iterate_once(or_ctx* x) {
             for (int k = 0; k < 5; ++k) g7_damp(&out[k], &x->nmsg[5 * (size_t)n + k], c->damping);
     }
 
+    if (c->store_fp32) {
+#pragma omp parallel for schedule(static)
+        for (int i = 0; i < N; ++i) {
+            for (int k = 0; k < 8; ++k) g7_round32(&x->newmsg[8 * (size_t)i + k]);
+            if (tree) g7_round32(&x->pnewmsg[i]);
+        }
+#pragma omp parallel for schedule(static)
+        for (int n = 0; n < NT; ++n)
+            for (int k = 0; k < 5; ++k) g7_round32(&x->nnewmsg[5 * (size_t)n + k]);
+    }
+
     /* U: new beliefs, means, relinearisation and message transport */
 #pragma omp parallel for schedule(static) reduction(| : fail)
     for (int i = 0; i < N; ++i) {
@@ -990,6 +1009,20 @@ static int iterate_once(or_ctx* x) {
         mat_mul(4, 4, 4, T0, Tm, T1);
         or_se3_log(T1, tn);
         for (int k = 0; k < 5; ++k) g7_transport(&mn[k], m);
+    }
+    if (c->store_fp32) {
+#pragma omp parallel for schedule(static)
+        for (int i = 0; i < N; ++i) {
+            for (int k = 0; k < 6; ++k) x->tau[6 * (size_t)i + k] = round32(x->tau[6 * (size_t)i + k]);
+            x->ell[i] = round32(x->ell[i]);
+            for (int k = 0; k < 8; ++k) g7_round32(&x->msg[8 * (size_t)i + k]);
+            if (tree) g7_round32(&x->pmsg[i]);
+        }
+#pragma omp parallel for schedule(static)
+        for (int n = 0; n < NT; ++n) {
+            for (int k = 0; k < 6; ++k) x->ntau[6 * (size_t)n + k] = round32(x->ntau[6 * (size_t)n + k]);
+            for (int k = 0; k < 5; ++k) g7_round32(&x->nmsg[5 * (size_t)n + k]);
+        }
     }
     if (fail) x->diverged = 1;
     return fail ? -1 : 0;

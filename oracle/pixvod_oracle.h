@@ -62,6 +62,9 @@ typedef struct {
     int frozen;                       /* never relinearise: linear GBP */
     int full_jacobian;                /* identity factor with exact Lie Jacobians */
     int topology;                     /* identity factors: OR_TOPO_GRID or OR_TOPO_QUADTREE */
+    int store_fp32;                   /* storage emulation: every new message is rounded to
+                                       * FP32 before the update uses it, and the linearisation
+                                       * points and stored messages after every iteration */
 } or_config;
 
 /* identity-factor topologies (Sec. 3.3, Fig. 2): the 4-neighbour pixel grid,

@@ -98,6 +98,7 @@ _SIGNATURES = {
     "pixvod_batch_autotune": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "pixvod_batch_last_step_ms": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "pixvod_batch_get_state": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int]),
+    "pixvod_batch_set_state": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int]),
     "pixvod_unroll_create": (C.c_int, [C.c_int, C.c_int, C.POINTER(Intrinsics), C.POINTER(Params), C.c_int, C.c_int,
                                        C.c_int, C.POINTER(C.c_void_p)]),
     "pixvod_unroll_destroy": (C.c_int, [C.c_void_p]),
@@ -168,7 +169,35 @@ def _ptr(a, dtype=np.float32):
     return arr.ctypes.data, HOST, arr
 
 
-class Tracker:
+class _FollowsTorchStream:
+    """Stream binding shared by the wrappers. A call that takes or returns
+    CUDA tensors runs on torch's current stream, so it is ordered after the
+    torch work that produced its inputs and before the work that reads its
+    outputs, unless set_stream() chose a stream explicitly. Binding a new
+    stream waits for the work already queued on the previous one."""
+
+    _explicit_stream = False
+    _bound_stream = None
+
+    def _bind_stream(self, handle):
+        raise NotImplementedError
+
+    def set_stream(self, stream=None):
+        s = None if stream is None else (stream.cuda_stream if hasattr(stream, "cuda_stream") else stream)
+        self._bind_stream(None if s is None else C.c_void_p(s))
+        self._explicit_stream = s is not None
+        self._bound_stream = s
+
+    def _follow_torch(self, *wheres):
+        if self._explicit_stream or DEVICE not in wheres:
+            return
+        cur = torch.cuda.current_stream().cuda_stream
+        if cur != self._bound_stream:
+            self._bind_stream(C.c_void_p(cur))
+            self._bound_stream = cur
+
+
+class Tracker(_FollowsTorchStream):
     """One image sequence: keyframe, target frames and the GBP state on the GPU."""
 
     def __init__(self, H: int, W: int, K, params: Optional[Params] = None, **overrides):
@@ -199,9 +228,8 @@ class Tracker:
     def __exit__(self, *a):
         self.close()
 
-    def set_stream(self, stream=None):
-        s = None if stream is None else C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else stream)
-        _check(lib().pixvod_set_stream(self._h, s), self._h)
+    def _bind_stream(self, handle):
+        _check(lib().pixvod_set_stream(self._h, handle), self._h)
 
     def set_schedule(self, schedule: int):
         _check(lib().pixvod_set_schedule(self._h, int(schedule)), self._h)
@@ -214,6 +242,7 @@ class Tracker:
         if wi != wn:
             raise ValueError("image and normals must live in the same memory")
         f = lib().pixvod_set_keyframe_transfer if transfer_depth else lib().pixvod_set_keyframe
+        self._follow_torch(wi)
         _check(f(self._h, C.c_void_p(pi), C.c_void_p(pn), wi), self._h)
 
     def set_sigma_map(self, sigma):
@@ -221,6 +250,7 @@ class Tracker:
             _check(lib().pixvod_set_sigma_map(self._h, None, HOST), self._h)
             return
         p, w, k = _ptr(sigma)
+        self._follow_torch(w)
         _check(lib().pixvod_set_sigma_map(self._h, C.c_void_p(p), w), self._h)
 
     def set_prior(self, xi=None, log_depth=None):
@@ -230,6 +260,7 @@ class Tracker:
             p, w, k = None, HOST, None
         else:
             p, w, k = _ptr(log_depth)
+        self._follow_torch(w)
         _check(lib().pixvod_set_prior(self._h, None if x is None else C.c_void_p(x.ctypes.data),
                                       None if p is None else C.c_void_p(p), w), self._h)
 
@@ -255,6 +286,7 @@ class Tracker:
                 out.inv_depth, out.inv_depth_var, out.out_where = inv.ctypes.data, var.ctypes.data, HOST
         else:
             out.out_where = HOST
+        self._follow_torch(wf, out.out_where)
         _check(lib().pixvod_track(self._h, C.c_void_p(pf), wf, int(n_iters), C.byref(out)), self._h)
         return dict(xi=np.array(out.xi_rel[:]), T_world=np.array(out.T_world[:]).reshape(4, 4),
                     valid_fraction=float(out.valid_fraction),
@@ -308,6 +340,7 @@ class Tracker:
             if s.size * 4 != self.state_bytes():
                 raise ValueError("state size does not match the context")
         p, w, k = _ptr(s)
+        self._follow_torch(w)
         _check(lib().pixvod_set_state(self._h, C.c_void_p(p), w), self._h)
 
 
@@ -317,7 +350,7 @@ def _batch_check(rc: int, h=None):
         raise PixvodError(rc, msg.decode() if msg else "")
 
 
-class Batch:
+class Batch(_FollowsTorchStream):
     """Many independent sequences (mixed resolutions) advanced together; one
     launch per pass over all sequences, frame steps replayed as HIP graphs."""
 
@@ -346,9 +379,8 @@ class Batch:
         except Exception:
             pass
 
-    def set_stream(self, stream=None):
-        s = None if stream is None else C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else stream)
-        _batch_check(lib().pixvod_batch_set_stream(self._h, s))
+    def _bind_stream(self, handle):
+        _batch_check(lib().pixvod_batch_set_stream(self._h, handle))
 
     def set_keyframes(self, seq_ids, imgs, normals):
         m = len(seq_ids)
@@ -364,6 +396,7 @@ class Batch:
             pi.append(a)
             pn.append(b)
         ids = (C.c_int * m)(*seq_ids)
+        self._follow_torch(where)
         _batch_check(lib().pixvod_batch_set_keyframes(self._h, m, ids, (C.c_void_p * m)(*pi), (C.c_void_p * m)(*pn),
                                                       HOST if where is None else where))
 
@@ -401,6 +434,7 @@ class Batch:
                 maps_out.append((inv, var))
             else:
                 maps_out.append((None, None))
+        self._follow_torch(where)
         _batch_check(lib().pixvod_batch_track(self._h, (C.c_void_p * self.n)(*ptrs), where, int(n_iters), outs))
         return [dict(xi=np.array(o.xi_rel[:]), T_world=np.array(o.T_world[:]).reshape(4, 4),
                      valid_fraction=float(o.valid_fraction), frames_since_keyframe=int(o.frames_since_keyframe),
@@ -413,8 +447,15 @@ class Batch:
         _batch_check(lib().pixvod_batch_get_state(self._h, int(seq), C.c_void_p(s.ctypes.data), HOST))
         return s
 
+    def set_state(self, seq: int, state: np.ndarray):
+        H, W = self.shapes[seq]
+        s = np.ascontiguousarray(state, dtype=np.float32)
+        if s.shape != (N_PLANES, H, W):
+            raise ValueError(f"state must be {(N_PLANES, H, W)}")
+        _batch_check(lib().pixvod_batch_set_state(self._h, int(seq), C.c_void_p(s.ctypes.data), HOST))
 
-class Unrolled:
+
+class Unrolled(_FollowsTorchStream):
     """Differentiable unrolled tracking of target frames against one keyframe.
 
     forward() runs n_iters GBP iterations per frame from the keyframe's
@@ -450,15 +491,15 @@ class Unrolled:
         except Exception:
             pass
 
-    def set_stream(self, stream=None):
-        s = None if stream is None else C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else stream)
-        _batch_check(lib().pixvod_unroll_set_stream(self._h, s))
+    def _bind_stream(self, handle):
+        _batch_check(lib().pixvod_unroll_set_stream(self._h, handle))
 
     def set_keyframe(self, img, normals):
         pi, wi, ki = _ptr(img)
         pn, wn, kn = _ptr(normals)
         if wi != wn:
             raise ValueError("image and normals must live in the same memory")
+        self._follow_torch(wi)
         _batch_check(lib().pixvod_unroll_set_keyframe(self._h, C.c_void_p(pi), C.c_void_p(pn), wi))
 
     def forward(self, frames, sigma_map, sigma_N: float, huber_k: float, out_device: bool = False):
@@ -474,6 +515,7 @@ class Unrolled:
         else:
             rho = np.empty((F, self.H, self.W), np.float32)
             pr, wr = rho.ctypes.data, HOST
+        self._follow_torch(wf, ws, wr)
         _batch_check(lib().pixvod_unroll_forward(self._h, C.c_void_p(pf), F, wf, C.c_void_p(ps), ws,
                                                  float(sigma_N), float(huber_k), C.c_void_p(xi.ctypes.data),
                                                  C.c_void_p(pr), wr))
@@ -494,6 +536,7 @@ class Unrolled:
             g = np.empty((self.H, self.W), np.float32)
             pg, wg = g.ctypes.data, HOST
         gN, gk = C.c_double(), C.c_double()
+        self._follow_torch(wr, wg)
         _batch_check(lib().pixvod_unroll_backward(self._h, None if xb is None else C.c_void_p(xb.ctypes.data),
                                                   None if pr is None else C.c_void_p(pr), wr, C.c_void_p(pg), wg,
                                                   C.byref(gN), C.byref(gk)))
@@ -533,7 +576,7 @@ def unrolled_track(unroll: Unrolled, frames, sigma_map, sigma_N, huber_k):
     return _UnrolledTrack.apply(unroll, frames, sigma_map, sigma_N, huber_k)
 
 
-class Central:
+class Central(_FollowsTorchStream):
     """Centralised IRLS Gauss-Newton baseline: one global pose and per-pixel
     log-depths, every pixel accessible at once (the normal equations solved by
     FP64 preconditioned conjugate gradients on the GPU)."""
@@ -561,15 +604,15 @@ class Central:
         except Exception:
             pass
 
-    def set_stream(self, stream=None):
-        s = None if stream is None else C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else stream)
-        _check(lib().pixvod_central_set_stream(self._h, s))
+    def _bind_stream(self, handle):
+        _check(lib().pixvod_central_set_stream(self._h, handle))
 
     def set_keyframe(self, img, normals):
         pi, wi, ki = _ptr(img)
         pn, wn, kn = _ptr(normals)
         if wi != wn:
             raise ValueError("img and normals must live in the same memory")
+        self._follow_torch(wi)
         _check(lib().pixvod_central_set_keyframe(self._h, C.c_void_p(pi), C.c_void_p(pn), wi))
 
     def set_point(self, xi=None, log_depth=None):
@@ -597,6 +640,7 @@ class Central:
             else:
                 inv = np.zeros((self.H, self.W), np.float32)
                 pinv = inv.ctypes.data
+        self._follow_torch(wf, DEVICE if (maps and out_device) else HOST)
         _check(lib().pixvod_central_track(self._h, C.c_void_p(pf), wf, int(n_iters), C.c_void_p(xi.ctypes.data),
                                           None if pinv is None else C.c_void_p(pinv),
                                           DEVICE if out_device else HOST, C.byref(st)))

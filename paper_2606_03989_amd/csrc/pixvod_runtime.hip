@@ -1286,6 +1286,24 @@ int pixvod_batch_get_state(pixvod_batch* b, int seq, void* dst, int where) {
     return PIXVOD_OK;
 }
 
+int pixvod_batch_set_state(pixvod_batch* b, int seq, const void* src, int where) {
+    if (!b) return bfail(nullptr, PIXVOD_EINVAL, "batch is NULL");
+    if (seq < 0 || seq >= b->n || !src) return bfail(b, PIXVOD_EINVAL, "bad sequence or source");
+    if (where != PIXVOD_HOST && where != PIXVOD_DEVICE) return bfail(b, PIXVOD_EINVAL, "bad location");
+    BatchSeq& q = b->seq[seq];
+    const size_t n = (size_t)N_PLANES * q.H * q.W;
+    const float* d = (const float*)src;
+    if (where == PIXVOD_HOST) {
+        if (!q.dense && hipMalloc((void**)&q.dense, n * sizeof(float)) != hipSuccess)
+            return bfail(b, PIXVOD_ENOMEM, "staging allocation failed");
+        HIP_TRY_B(b, hipMemcpyAsync(q.dense, src, n * sizeof(float), hipMemcpyHostToDevice, b->stream));
+        d = q.dense;
+    }
+    HIP_TRY_B(b, launch_pack_state(geo_of_seq(q), q.X[b->parity], const_cast<float*>(d), 0, b->stream));
+    HIP_TRY_B(b, hipStreamSynchronize(b->stream));
+    return PIXVOD_OK;
+}
+
 int pixvod_batch_autotune(pixvod_batch* b, int n_iters, int* tx_out, int* ty_out) {
     if (!b) return bfail(nullptr, PIXVOD_EINVAL, "batch is NULL");
     if (n_iters < 1 || !tx_out || !ty_out) return bfail(b, PIXVOD_EINVAL, "bad autotune arguments");

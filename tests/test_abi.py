@@ -65,9 +65,13 @@ def test_argument_validation_precedes_device_use():
     assert _create(24, 32, K, bad)[0] == pv.EINVAL
     bad = pv.default_params(huber_k=float("nan"))
     assert _create(24, 32, K, bad)[0] == pv.EINVAL
-    assert pv.lib().pixvod_create(24, 32, C.byref(pv.Intrinsics(*K)), None, None) == pv.EINVAL
     # context-free calls report through the thread-local message
-    assert b"H and W" in pv.lib().pixvod_last_error(None) or True
+    assert _create(1, 32, K)[0] == pv.EINVAL
+    assert b"H and W" in pv.lib().pixvod_last_error(None)
+    assert _create(24, 32, (0.0, 30.0, 16.0, 12.0))[0] == pv.EINVAL
+    assert b"intrinsics" in pv.lib().pixvod_last_error(None)
+    assert pv.lib().pixvod_create(24, 32, C.byref(pv.Intrinsics(*K)), None, None) == pv.EINVAL
+    assert b"out_ctx" in pv.lib().pixvod_last_error(None)
     # NULL-context calls
     assert pv.lib().pixvod_track(None, None, 0, 1, None) == pv.EINVAL
     assert pv.lib().pixvod_set_keyframe(None, None, None, 0) == pv.EINVAL

@@ -168,3 +168,38 @@ def test_autograd_function():
     assert abs(sN.grad.item() - gN) <= 1e-9 * abs(gN) + 1e-15
     assert abs(hk.grad.item() - gk) <= 1e-9 * abs(gk) + 1e-15
     u.close()
+
+
+def test_device_inputs_follow_torch_stream():
+    # A float64 sigma map computed on the device by torch ops just before the
+    # call, behind long-running work on torch's stream: the library's work is
+    # ordered after it (it runs on torch's current stream), so the outputs equal
+    # those of host inputs bit for bit, and the gradients those of the direct
+    # backward call.
+    import paper_2606_03989_amd as pv
+    w = diff_crop_workload(32, 2)
+    frames_np = np.stack(w["frames"]).astype(np.float32)
+    u_host = make_unroll(w, 10, 4)
+    xi_h, rho_h = u_host.forward(frames_np, w["sigma_map"], w["sigma_N"], w["huber_k"])
+    u = make_unroll(w, 10, 4)
+    dev = torch.device("cuda")
+    frames = torch.from_numpy(frames_np).to(dev)
+    x = torch.randn(3072, 3072, device=dev)
+    for _ in range(6):
+        x = torch.tanh(x @ x)                   # keeps torch's stream busy
+    sig = torch.from_numpy(w["sigma_map"].astype(np.float64)).to(dev) + 0.0 * x[0, 0].double()
+    sig.requires_grad_(True)
+    sN = torch.tensor(w["sigma_N"], dtype=torch.float64, device=dev, requires_grad=True)
+    hk = torch.tensor(w["huber_k"], dtype=torch.float64, device=dev, requires_grad=True)
+    xi, rho = pv.unrolled_track(u, frames, sig, sN, hk)
+    np.testing.assert_array_equal(xi.detach().cpu().numpy(), xi_h)
+    np.testing.assert_array_equal(rho.detach().cpu().numpy(), rho_h)
+    loss = (xi ** 2).sum() + ((rho - 0.5) ** 2).mean()
+    loss.backward()
+    cx = (2 * xi).detach().cpu().numpy()
+    cr = (2 * (rho - 0.5) / rho.numel()).detach().cpu().numpy()
+    g, gN, gk = u_host.backward(cx, cr)
+    np.testing.assert_allclose(sig.grad.cpu().numpy(), g, rtol=1e-6, atol=1e-9 * np.abs(g).max())
+    assert abs(sN.grad.item() - gN) <= 1e-9 * abs(gN) + 1e-15
+    u.close()
+    u_host.close()

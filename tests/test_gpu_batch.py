@@ -1,11 +1,15 @@
-"""Batched tracking (many sequences of mixed resolution per launch): the batch
-must reproduce per-sequence contexts bit for bit, for every tile shape, and
-its frame-step graph must replay consistently."""
+"""Batched tracking (many sequences of mixed resolution per launch): every
+sequence of a batch is checked against the FP64 oracle (one iteration from an
+identical state, and a free-running frame), the batch must reproduce
+per-sequence contexts bit for bit, for every tile shape, and its frame-step
+graph must replay consistently."""
 
 import numpy as np
 import pytest
 
 import synth
+from parity import (check_free_running, check_iteration, from_oracle, iteration_spread, make_oracle,
+                    oracle_spread, plane_errors, to_oracle)
 
 pytestmark = pytest.mark.gpu
 
@@ -42,6 +46,48 @@ def _make_batch(seqs, tile=None):
 
 
 SHAPES = [(24, 32), (29, 37), (48, 64), (7, 130)]
+
+
+def _oracle_workload(s, frame, iters):
+    return dict(cam=s["cam"], I_s=s["I_s"], N_s=s["N_s"], frames=[frame], iters=iters, kw=dict(PARAMS))
+
+
+def test_batch_against_oracle():
+    # free-running first frame of every sequence (15 iterations, the batched
+    # workload's count), then one iteration of every sequence from a state
+    # loaded identically into batch and oracle (all 123 planes)
+    seqs = _seq_inputs(SHAPES, 2)
+    b = _make_batch(seqs)
+    iters = 15
+    rb = b.track([s["frames"][0] for s in seqs], iters, maps=True)
+    for i, s in enumerate(seqs):
+        w = _oracle_workload(s, s["frames"][0], iters)
+        o = make_oracle(w)
+        ro = o.track(s["frames"][0], iters)
+        spread = oracle_spread(w, s["frames"][0], iters, ref=ro)
+        check_free_running(rb[i], ro, spread, f"batch sequence {i} ({s['cam'].H}x{s['cam'].W}) frame 1")
+        assert rb[i]["frames_since_keyframe"] == ro["frames_since_keyframe"] == 1
+        o.close()
+    starts = []
+    for i, s in enumerate(seqs):
+        w = _oracle_workload(s, s["frames"][1], iters)
+        o = make_oracle(w)
+        o.track(s["frames"][1], 3)
+        s32 = from_oracle(o.get_state())
+        b.set_state(i, s32)
+        np.testing.assert_array_equal(b.get_state(i), s32)
+        starts.append((w, s32))
+        o.close()
+    b.track([s["frames"][1] for s in seqs], 1)
+    for i, (w, s32) in enumerate(starts):
+        o = make_oracle(w)
+        o.set_state(to_oracle(s32))
+        o.set_frame(w["frames"][0])
+        o.iterate(1)
+        err = plane_errors(b.get_state(i), from_oracle(o.get_state()))
+        spread = iteration_spread(w, s32, w["frames"][0]) if err.max() > 1e-5 else None
+        check_iteration(err, spread, f"batch sequence {i} one iteration")
+        o.close()
 
 
 def test_batch_equals_per_sequence_contexts():

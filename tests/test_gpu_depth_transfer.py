@@ -20,6 +20,31 @@ def _state_with_motion(w, xi, seed):
     return np.ascontiguousarray(np.transpose(st, (2, 0, 1)).astype(np.float32))
 
 
+def _ambiguous_targets(ell, xi, cam, delta=1e-9):
+    """Target pixels whose winner can depend on rounding: those a source point
+    reaches from a splat coordinate within `delta` of a rounding boundary
+    (both neighbouring targets are marked). Computed independently here in
+    FP64 from the transfer's definition."""
+    H, W = ell.shape
+    T = oracle.se3_exp(xi)
+    v, u = np.mgrid[0:H, 0:W].astype(np.float64)
+    d = np.exp(ell.astype(np.float64))
+    P = np.stack([d * (u - cam.cx) / cam.fx, d * (v - cam.cy) / cam.fy, d], axis=-1)
+    Q = P @ T[:3, :3].T + T[:3, 3]
+    ok = Q[..., 2] > 0
+    uu = cam.fx * Q[..., 0] / Q[..., 2] + cam.cx + 0.5
+    vv = cam.fy * Q[..., 1] / Q[..., 2] + cam.cy + 0.5
+    amb = np.zeros((H, W), bool)
+    fu, fv = uu - np.floor(uu), vv - np.floor(vv)
+    near = ok & ((np.minimum(fu, 1 - fu) < delta) | (np.minimum(fv, 1 - fv) < delta))
+    for i in zip(*np.nonzero(near)):
+        for ju in {int(np.floor(uu[i])), int(np.floor(uu[i] - delta)), int(np.floor(uu[i] + delta))}:
+            for jv in {int(np.floor(vv[i])), int(np.floor(vv[i] - delta)), int(np.floor(vv[i] + delta))}:
+                if 0 <= ju < W and 0 <= jv < H:
+                    amb[jv, ju] = True
+    return amb, int(near.sum())
+
+
 @pytest.mark.parametrize("kind", ["tiny", "ppa256"])
 def test_transfer_matches_oracle(kind):
     w = tiny_workload() if kind == "tiny" else sequence_workload("ppa256", 1)
@@ -39,14 +64,18 @@ def test_transfer_matches_oracle(kind):
     g = t.get_state()[6].astype(np.float64)
     r = o.get_state()[..., 6]
     moved = r != s32[6].astype(np.float64)
+    # both sides store log of the winning FP32 depth: equal up to the FP32
+    # storage of that log, or a one-ulp different FP32 depth of the same winner
     e = np.abs(g - r)
-    frac_exact = float(np.mean(e <= 1e-6 * np.maximum(1.0, np.abs(r))))
-    print(f"{kind}: {moved.mean():.3f} of the pixels received a point; agreement within FP32 storage "
-          f"{frac_exact:.5f}; max error {e.max():.2e}", flush=True)
+    agree = e <= 1e-6 * np.maximum(1.0, np.abs(r))
+    amb, n_near = _ambiguous_targets(s32[6], ro["xi"], w["cam"])
+    bad = ~agree
+    print(f"{kind}: {moved.mean():.3f} of the pixels received a point; {int(bad.sum())} of {bad.size} differ "
+          f"beyond FP32 storage (max error {e.max():.2e}); {n_near} source points within 1e-9 px of a "
+          f"rounding boundary mark {int(amb.sum())} targets", flush=True)
     assert 0.3 < moved.mean() < 1.0
-    # a winner decided by a last-bit difference of the pose may differ at a
-    # handful of pixels
-    assert frac_exact >= 0.999
+    # every difference is a proven rounding tie of the splat coordinate
+    assert not np.any(bad & ~amb), np.argwhere(bad & ~amb)[:10]
     # the rest of the state is the keyframe reset
     st = t.get_state()
     assert np.all(st[:6] == 0) and np.all(st[7:] == 0)

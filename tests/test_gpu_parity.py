@@ -1,5 +1,6 @@
 """GPU parity: the HIP path through the C-ABI against the FP64 oracle on the
-same seeded inputs."""
+same seeded inputs. Bounds: the fixed bar or twice the oracle's own spread at
+the GPU's storage precision, whichever is larger (see tests/parity.py)."""
 
 import math
 
@@ -7,12 +8,22 @@ import numpy as np
 import pytest
 
 import oracle
-from parity import (DEPTH_TOL, POSE_TOL, depth_agreement, from_oracle, make_oracle, make_tracker,
-                    pose_agreement, sequence_workload, tiny_workload, to_oracle)
+from parity import (DEPTH_TOL, POSE_TOL, check_free_running, check_iteration, depth_agreement, from_oracle,
+                    iteration_spread, make_oracle, make_tracker, oracle_spread, plane_errors, pose_agreement,
+                    sequence_workload, tiny_workload, to_oracle)
 
 pytestmark = pytest.mark.gpu
 
 SCHEDULES = [0, 1]   # fused, per-factor
+
+_SPREADS = {}
+
+
+def _spread(key, w, frame, n_iters, start=None, ref=None):
+    """The oracle's free-running spread of a workload, computed once per key."""
+    if key not in _SPREADS:
+        _SPREADS[key] = oracle_spread(w, frame, n_iters, start=start, ref=ref)
+    return _SPREADS[key]
 
 
 def _run_both(w, schedule, n_frames=None):
@@ -27,16 +38,14 @@ def _run_both(w, schedule, n_frames=None):
     return t, o, out
 
 
-def _assert_frame(rg, ro, name, depth_max=5e-2):
-    dp = pose_agreement(rg["xi"], ro["xi"])
-    da = depth_agreement(rg["inv_depth"], ro["inv_depth"])
-    print(f"{name}: pose {dp:.2e} depth rms {da['rms']:.2e} p99 {da['p99']:.2e} max {da['max']:.2e} "
-          f"frac>tol {da['frac_over']:.2e} valid {rg['valid_fraction']:.4f}/{ro['valid_fraction']:.4f}", flush=True)
-    assert dp <= POSE_TOL
-    assert da["rms"] <= DEPTH_TOL and da["p99"] <= DEPTH_TOL
-    assert da["max"] <= depth_max
-    assert abs(rg["valid_fraction"] - ro["valid_fraction"]) <= 2e-3
-    assert (rg["flags"] & oracle.DIVERGED) == (ro["flags"] & oracle.DIVERGED)
+def _free_frame_1(w, schedule, key, name):
+    """Frame 1 free-running from the keyframe state, checked against the bar
+    or the oracle's spread."""
+    t, o, out = _run_both(w, schedule, 1)
+    rg, ro = out[0]
+    spread = _spread(key, w, w["frames"][0], w["iters"], ref=ro)
+    check_free_running(rg, ro, spread, name)
+    return t, o, rg, ro
 
 
 # --- one iteration from an identical state ---------------------------------------
@@ -52,26 +61,26 @@ def _one_step(t, o, state32, frame):
     return t.get_state(), from_oracle(o.get_state())
 
 
-def _plane_errors(g, r):
-    g = g.astype(np.float64)
-    r = r.astype(np.float64)
-    scale = np.abs(r).reshape(123, -1).max(axis=1)[:, None, None] + 1e-30
-    return np.abs(g - r) / scale
+def _condition_at(o, worst):
+    """Condition number of the oracle's belief (the one its update solved) at
+    the pixel of the worst element."""
+    lam, _ = o.beliefs()
+    return float(np.linalg.cond(lam[worst[1], worst[2]]))
 
 
 SINGLE_CASES = {
-    # name: (workload factory, p99.9 bound, fraction of elements above 1e-5)
-    "tiny_sigmaP1": (lambda: tiny_workload(sigma_P=1.0), 1e-3, 2e-2),
-    "tiny": (lambda: tiny_workload(huber_k=10.0), 1e-5, 1e-3),
-    "ppa256": (lambda: sequence_workload("ppa256", 1), 1e-5, 2e-3),
+    # the paper's strengths on the tiny pair (sigma_P = 1): beliefs with
+    # condition numbers ~1e5, the corner pixels' poses most sensitive
+    "tiny_sigmaP1": lambda: tiny_workload(sigma_P=1.0),
+    "tiny": lambda: tiny_workload(huber_k=10.0),
+    "ppa256": lambda: sequence_workload("ppa256", 1),
 }
 
 
 @pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("case", list(SINGLE_CASES))
 def test_single_iteration_from_identical_state(case, schedule):
-    make, p999, frac_bound = SINGLE_CASES[case]
-    w = make()
+    w = SINGLE_CASES[case]()
     # a non-trivial state: the oracle after a few iterations, rounded to FP32
     o = make_oracle(w)
     o.track(w["frames"][0], 3)
@@ -81,13 +90,30 @@ def test_single_iteration_from_identical_state(case, schedule):
     t.set_state(s32)
     np.testing.assert_array_equal(t.get_state(), s32)
     g, r = _one_step(t, o, s32, w["frames"][0])
-    err = _plane_errors(g, r)
+    err = plane_errors(g, r)
     worst = np.unravel_index(np.argmax(err), err.shape)
-    q = float(np.percentile(err, 99.9))
-    frac = float(np.mean(err > 1e-5))
-    print(f"{case}/{schedule}: plane-relative error p99.9 {q:.2e} max {err.max():.2e} at {worst} "
-          f"frac>1e-5 {frac:.2e}", flush=True)
-    assert q <= p999 and frac <= frac_bound
+    print(f"{case}/{schedule}: belief condition number at the worst pixel {_condition_at(o, worst):.2e}; "
+          f"fraction of elements above 1e-5 {float(np.mean(err > 1e-5)):.2e}", flush=True)
+    check_iteration(err, iteration_spread(w, s32, w["frames"][0]), f"{case}/{schedule}")
+
+
+def _teacher_forced(t, o, w, frame, n, label, setup=None):
+    """n iterations, the oracle restarted from the GPU's state before each;
+    every iteration's maximum and p99.9 bounded (the oracle's own spread is
+    computed only for an iteration whose error exceeds the fixed bar)."""
+    worst = [0.0, 0.0]
+    for it in range(n):
+        s32 = t.get_state()
+        o.set_state(to_oracle(s32))
+        t.iterate(1)
+        o.iterate(1)
+        err = plane_errors(t.get_state(), from_oracle(o.get_state()))
+        mx, q = float(err.max()), float(np.percentile(err, 99.9))
+        if mx > 1e-5 or q > 1e-5:
+            check_iteration(err, iteration_spread(w, s32, frame, setup=setup), f"{label} iteration {it}")
+        worst = [max(worst[0], mx), max(worst[1], q)]
+    print(f"{label}: {n} teacher-forced iterations, worst max {worst[0]:.2e} p99.9 {worst[1]:.2e}", flush=True)
+    return worst
 
 
 def test_teacher_forced_iterations_ppa256():
@@ -97,17 +123,7 @@ def test_teacher_forced_iterations_ppa256():
     o = make_oracle(w)
     t.track(w["frames"][0], 0)
     o.set_frame(w["frames"][0])
-    worst = 0.0
-    for it in range(w["iters"]):
-        s32 = t.get_state()
-        o.set_state(to_oracle(s32))
-        t.iterate(1)
-        o.iterate(1)
-        err = _plane_errors(t.get_state(), from_oracle(o.get_state()))
-        q = float(np.percentile(err, 99.9))
-        worst = max(worst, q)
-        assert q <= 1e-5, f"iteration {it}: p99.9 {q:.2e}"
-    print(f"ppa256 teacher-forced 20 iterations: worst p99.9 {worst:.2e}", flush=True)
+    _teacher_forced(t, o, w, w["frames"][0], w["iters"], "ppa256")
 
 
 # --- free-running parity ---------------------------------------------------------
@@ -116,19 +132,44 @@ def test_teacher_forced_iterations_ppa256():
 @pytest.mark.parametrize("huber_k", [400.0, 10.0])
 def test_tiny_pair_50_iterations(schedule, huber_k):
     w = tiny_workload(huber_k=huber_k)
-    t, o, out = _run_both(w, schedule)
-    rg, ro = out[0]
-    _assert_frame(rg, ro, f"tiny k={huber_k} sched={schedule}")
+    t, o, rg, ro = _free_frame_1(w, schedule, ("tiny", huber_k), f"tiny k={huber_k} sched={schedule}")
     # outputs: variance of the final belief, finite and positive
     assert np.all(np.isfinite(rg["inv_depth_var"])) and np.all(rg["inv_depth_var"] > 0)
     np.testing.assert_allclose(rg["inv_depth_var"], ro["inv_depth_var"], rtol=1e-3)
 
 
 @pytest.mark.parametrize("schedule", SCHEDULES)
+@pytest.mark.parametrize("huber_k", [400.0, 10.0])
+def test_tiny_pair_paper_strengths_50_iterations(schedule, huber_k):
+    # the 32x24 pair with the paper's leaf strengths (sigma_P = 1, Sec. 4.2)
+    # over 50 free-running iterations. The first iteration after the keyframe
+    # takes pose steps up to ~1 rad along weakly determined directions
+    # (belief condition numbers 1e4 to 1e5): the FP32 storage of the messages
+    # alone moves the oracle's own result by up to ~3e-3 in pose, so the
+    # bound is the oracle's spread at that storage precision
+    w = tiny_workload(sigma_P=1.0, huber_k=huber_k)
+    t, o, rg, ro = _free_frame_1(w, schedule, ("tiny_sigmaP1", huber_k),
+                                 f"tiny sigma_P=1 k={huber_k} sched={schedule}")
+    assert np.all(np.isfinite(rg["inv_depth_var"])) and np.all(rg["inv_depth_var"] > 0)
+
+
+@pytest.mark.parametrize("huber_k", [400.0, 10.0])
+def test_teacher_forced_tiny_pair_paper_strengths(huber_k):
+    # all 50 iterations of the 32x24 pair at sigma_P = 1, the oracle restarted
+    # from the GPU's state before each: config 1's comparison without the
+    # free-running horizon's sensitivity
+    w = tiny_workload(sigma_P=1.0, huber_k=huber_k)
+    t = make_tracker(w, 0)
+    o = make_oracle(w)
+    t.track(w["frames"][0], 0)
+    o.set_frame(w["frames"][0])
+    _teacher_forced(t, o, w, w["frames"][0], w["iters"], f"tiny sigma_P=1 k={huber_k}")
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
 def test_ppa256_frame_1(schedule):
     w = sequence_workload("ppa256", 1)
-    t, o, out = _run_both(w, schedule)
-    _assert_frame(out[0][0], out[0][1], f"ppa256 frame 1 sched={schedule}")
+    _free_frame_1(w, schedule, "ppa256", f"ppa256 frame 1 sched={schedule}")
 
 
 def test_ppa256_teacher_forced_frames():
@@ -139,11 +180,13 @@ def test_ppa256_teacher_forced_frames():
     t.track(w["frames"][0], w["iters"])
     o.track(w["frames"][0], 0)
     for k in (1, 2):
-        o.set_state(to_oracle(t.get_state()))
+        start = to_oracle(t.get_state())
+        o.set_state(start)
         rg = t.track(w["frames"][k], w["iters"])
         ro = o.track(w["frames"][k], w["iters"])
         assert rg["frames_since_keyframe"] == ro["frames_since_keyframe"] == k + 1
-        _assert_frame(rg, ro, f"ppa256 frame {k + 1} teacher-forced")
+        spread = oracle_spread(w, w["frames"][k], w["iters"], start=start, ref=ro)
+        check_free_running(rg, ro, spread, f"ppa256 frame {k + 1} teacher-forced")
 
 
 @pytest.mark.parametrize("setting", ["mild", "strong"])
@@ -159,48 +202,36 @@ def test_teacher_forced_iterations_sensor_noise(setting):
     o = make_oracle(w)
     t.track(w["frames"][0], 0)
     o.set_frame(w["frames"][0])
-    worst = 0.0
-    for it in range(w["iters"]):
-        o.set_state(to_oracle(t.get_state()))
-        t.iterate(1)
-        o.iterate(1)
-        q = float(np.percentile(_plane_errors(t.get_state(), from_oracle(o.get_state())), 99.9))
-        worst = max(worst, q)
-        assert q <= 1e-5, f"{setting} iteration {it}: p99.9 {q:.2e}"
-    print(f"ppa256 {setting} sensor noise, teacher-forced 20 iterations: worst p99.9 {worst:.2e}", flush=True)
+    _teacher_forced(t, o, w, w["frames"][0], w["iters"], f"ppa256 {setting} sensor noise")
 
 
 def test_vga_frame_1():
     w = sequence_workload("vga", 1)
-    t, o, out = _run_both(w, 0)
-    _assert_frame(out[0][0], out[0][1], "vga frame 1")
+    _free_frame_1(w, 0, "vga", "vga frame 1")
 
 
 @pytest.mark.parametrize("case", ["tiny", "ppa256"])
 def test_schedules_agree(case):
-    # the fused and per-factor schedules evaluate the same arithmetic
+    # the fused and per-factor schedules evaluate the same arithmetic in the
+    # same order: bit-identical states and pose estimates
     w = tiny_workload(huber_k=10.0) if case == "tiny" else sequence_workload("ppa256", 1)
     res = []
     for sched in SCHEDULES:
         t = make_tracker(w, sched)
         r = t.track(w["frames"][0], 10)
         res.append((r, t.get_state()))
-    same = np.array_equal(res[0][1], res[1][1])
-    d = np.abs(res[0][1].astype(np.float64) - res[1][1]).reshape(123, -1).max(axis=1)
-    scale = np.abs(res[1][1]).reshape(123, -1).max(axis=1) + 1e-30
-    print(f"{case}: schedules bit-identical: {same}; max plane-relative difference {(d / scale).max():.2e}", flush=True)
-    assert pose_agreement(res[0][0]["xi"], res[1][0]["xi"]) <= 1e-7
-    assert np.all(d / scale < 1e-4)
+    print(f"{case}: schedules bit-identical: {np.array_equal(res[0][1], res[1][1])}", flush=True)
+    np.testing.assert_array_equal(res[0][1], res[1][1])
+    np.testing.assert_array_equal(res[0][0]["xi"], res[1][0]["xi"])
+    np.testing.assert_array_equal(res[0][0]["inv_depth"], res[1][0]["inv_depth"])
+    np.testing.assert_array_equal(res[0][0]["inv_depth_var"], res[1][0]["inv_depth_var"])
 
 
 def test_damping_per_factor_schedule():
     w = tiny_workload(sigma_P=0.1)
     w["kw"]["damping"] = 0.3
-    t = make_tracker(w, 1)
-    o = make_oracle(w)
-    rg = t.track(w["frames"][0], 30)
-    ro = o.track(w["frames"][0], 30)
-    _assert_frame(rg, ro, "tiny damping 0.3")
+    w["iters"] = 30
+    _free_frame_1(w, 1, "tiny_damping", "tiny damping 0.3")
 
 
 # --- the boundary's behaviour on the GPU --------------------------------------------------
@@ -267,11 +298,7 @@ def test_ragged_and_minimal_shapes(shape):
     w = dict(cam=p["cam"], I_s=p["I_s"], N_s=p["normals_s"], frames=[p["I_t"]], iters=8,
              kw=dict(init_inv_depth=0.4, huber_k=10.0, sigma_P=0.1))
     for sched in SCHEDULES:
-        t = make_tracker(w, sched)
-        o = make_oracle(w)
-        rg = t.track(w["frames"][0], 8)
-        ro = o.track(w["frames"][0], 8)
-        _assert_frame(rg, ro, f"shape {shape} sched={sched}")
+        _free_frame_1(w, sched, ("shape", shape), f"shape {shape} sched={sched}")
 
 
 def test_constant_image_keeps_pose_at_identity():
@@ -295,22 +322,11 @@ def test_sigma_map_matches_oracle():
     o.set_sigma_D_map(sig.astype(np.float64))
     rg = t.track(w["frames"][0], 30)
     ro = o.track(w["frames"][0], 30)
-    _assert_frame(rg, ro, "sigma map")
+    # the tiny pair at sigma_P = 0.1 is well conditioned: the fixed bar
+    check_free_running(rg, ro, (0.0, dict(rms=0.0, p99=0.0, max=0.0, valid=0.0)), "sigma map")
 
 
 # --- prior means set at run time (temporal priors) ----------------------------------
-
-def _teacher_forced(t, o, n, label):
-    worst = 0.0
-    for it in range(n):
-        o.set_state(to_oracle(t.get_state()))
-        t.iterate(1)
-        o.iterate(1)
-        q = float(np.percentile(_plane_errors(t.get_state(), from_oracle(o.get_state())), 99.9))
-        worst = max(worst, q)
-        assert q <= 1e-5, f"{label} iteration {it}: p99.9 {q:.2e}"
-    print(f"{label}: worst p99.9 over {n} iterations {worst:.2e}", flush=True)
-
 
 def test_explicit_prior_means():
     w = sequence_workload("ppa256", 1)
@@ -323,7 +339,8 @@ def test_explicit_prior_means():
     o.set_prior(xi, ell.astype(np.float64))
     t.track(w["frames"][0], 0)
     o.set_frame(w["frames"][0])
-    _teacher_forced(t, o, 8, "explicit prior means")
+    _teacher_forced(t, o, w, w["frames"][0], 8, "explicit prior means",
+                    setup=lambda oo: oo.set_prior(xi, ell.astype(np.float64)))
 
 
 @pytest.mark.parametrize("schedule", SCHEDULES)
@@ -333,12 +350,18 @@ def test_temporal_prior_from_state(schedule):
     t = make_tracker(w, schedule)
     o = make_oracle(w)
     t.track(w["frames"][0], w["iters"])
-    o.set_state(to_oracle(t.get_state()))
+    start = to_oracle(t.get_state())
+    o.set_state(start)
     t.set_prior_from_state()
     o.set_prior_from_state()
     t.track(w["frames"][1], 0)
     o.set_frame(w["frames"][1])
-    _teacher_forced(t, o, 8, f"temporal prior sched={schedule}")
+
+    def setup(oo):
+        oo.set_state(start)
+        oo.set_prior_from_state()
+
+    _teacher_forced(t, o, w, w["frames"][1], 8, f"temporal prior sched={schedule}", setup=setup)
 
 
 def test_prior_errors_and_keyframe_reset():

@@ -8,21 +8,13 @@ import pytest
 
 import oracle
 import synth
-from parity import (DEPTH_TOL, POSE_TOL, K_of, depth_agreement, make_oracle, make_tracker, pose_agreement,
-                    sequence_workload, tiny_workload, tree_from_oracle, tree_to_oracle)
+from parity import (SINGLE_BAR, K_of, check_free_running, check_iteration, iteration_spread, make_oracle,
+                    make_tracker, oracle_spread, plane_errors, sequence_workload, tiny_workload, tree_from_oracle,
+                    tree_to_oracle)
 
 pytestmark = pytest.mark.gpu
 
 QT = oracle.TOPO_QUADTREE
-
-
-def _rel_errors(g, r):
-    """Per-plane relative errors of a (planes, ...) pair, scaled by the
-    oracle plane's largest magnitude."""
-    g = g.astype(np.float64).reshape(g.shape[0], -1)
-    r = r.astype(np.float64).reshape(r.shape[0], -1)
-    scale = np.abs(r).max(axis=1)[:, None] + 1e-30
-    return np.abs(g - r) / scale
 
 
 def _one_step(t, o, s32):
@@ -33,17 +25,18 @@ def _one_step(t, o, s32):
     return t.get_state(), tree_from_oracle(o.get_state())
 
 
-def _compare(g, r, name, p999=1e-5, frac_bound=2e-3):
+def _compare(g, r, name, spread_fn=None):
+    """Maximum and p99.9 of the plane-relative errors of the pixel and node
+    parts, each within 1e-5 or twice the oracle's own change of that part under
+    an FP32-resolution perturbation of the starting state (computed by
+    spread_fn only when an error exceeds the fixed bar)."""
     out = {}
-    for part, gi, ri in (("pixels", g[0], r[0]), ("nodes", g[1], r[1])):
-        err = _rel_errors(gi, ri)
-        q = float(np.percentile(err, 99.9))
-        frac = float(np.mean(err > 1e-5))
-        worst = np.unravel_index(np.argmax(err), err.shape)
-        print(f"{name} {part}: plane-relative p99.9 {q:.2e} max {err.max():.2e} at plane/index {worst} "
-              f"frac>1e-5 {frac:.2e}", flush=True)
-        out[part] = (q, frac)
-        assert q <= p999 and frac <= frac_bound, f"{name} {part}"
+    parts = (("pixels", g[0], r[0]), ("nodes", g[1], r[1]))
+    errs = {part: plane_errors(gi, ri) for part, gi, ri in parts}
+    over = any(float(e.max()) > SINGLE_BAR for e in errs.values())
+    spread = spread_fn() if (over and spread_fn is not None) else None
+    for part, err in errs.items():
+        out[part] = check_iteration(err, None if spread is None else spread[part], f"{name} {part}")
     return out
 
 
@@ -105,7 +98,7 @@ def test_single_iteration_from_identical_state(kind):
     t = make_tracker(w, 0, QT)
     t.track(w["frames"][0], 0)          # stages the frame
     g, r = _one_step(t, o, s32)
-    _compare(g, r, f"quadtree {kind}")
+    _compare(g, r, f"quadtree {kind}", lambda: iteration_spread(w, s32, w["frames"][0], QT))
 
 
 def test_teacher_forced_iterations_ppa256():
@@ -120,39 +113,22 @@ def test_teacher_forced_iterations_ppa256():
         o.set_state(tree_to_oracle(s32))
         t.iterate(1)
         o.iterate(1)
-        res = _compare(t.get_state(), tree_from_oracle(o.get_state()), f"iteration {it}")
+        res = _compare(t.get_state(), tree_from_oracle(o.get_state()), f"iteration {it}",
+                       lambda: iteration_spread(w, s32, w["frames"][0], QT))
         for k in worst:
             worst[k] = max(worst[k], res[k][0])
     print(f"ppa256 quadtree teacher-forced {w['iters']} iterations: worst p99.9 {worst}", flush=True)
 
 
-def _oracle_spread(w, ro):
-    """How far the oracle's own frame moves when its starting log-depths are
-    perturbed at FP32 resolution (uniform +-6e-8, the size of the GPU's
-    storage rounding): the conditioning of the free-running frame, below
-    which GPU and oracle cannot be told apart."""
-    o2 = make_oracle(w, QT)
-    pix, nodes = o2.get_state()
-    pix[..., 6] += 6e-8 * np.random.default_rng(0).uniform(-1, 1, pix[..., 6].shape)
-    o2.set_state((pix, nodes))
-    r2 = o2.track(w["frames"][0], w["iters"])
-    o2.close()
-    return pose_agreement(ro["xi"], r2["xi"]), depth_agreement(ro["inv_depth"], r2["inv_depth"])
-
-
-def _assert_frame(rg, ro, name, spread):
-    dp = pose_agreement(rg["xi"], ro["xi"])
-    da = depth_agreement(rg["inv_depth"], ro["inv_depth"])
-    sp, sd = spread
-    print(f"{name}: pose {dp:.2e} depth rms {da['rms']:.2e} p99 {da['p99']:.2e} max {da['max']:.2e} "
-          f"valid {rg['valid_fraction']:.4f}/{ro['valid_fraction']:.4f}; oracle spread pose {sp:.2e} "
-          f"rms {sd['rms']:.2e} p99 {sd['p99']:.2e}; xi {np.round(rg['xi'], 5)}", flush=True)
+def _assert_frame(w, rg, ro, name):
     # the fixed parity bar, or twice the oracle's own spread where the frame
-    # is worse conditioned than that bar
-    assert dp <= max(POSE_TOL, 2.0 * sp)
-    assert da["rms"] <= max(DEPTH_TOL, 2.0 * sd["rms"]) and da["p99"] <= max(DEPTH_TOL, 2.0 * sd["p99"])
-    assert abs(rg["valid_fraction"] - ro["valid_fraction"]) <= 2e-3
+    # is worse conditioned than that bar: the upper levels' strong priors and
+    # identity factors (up to 4^10 times the leaf precision at 640x480) make
+    # the free-running frame worse conditioned than on the grid
+    spread = oracle_spread(w, w["frames"][0], w["iters"], topology=QT, ref=ro)
+    check_free_running(rg, ro, spread, name)
     assert (rg["flags"] & oracle.DIVERGED) == (ro["flags"] & oracle.DIVERGED) == 0
+    print(f"{name}: xi {np.round(rg['xi'], 5)}", flush=True)
 
 
 @pytest.mark.parametrize("kind", ["tiny", "ppa256"])
@@ -162,7 +138,7 @@ def test_free_running_frame(kind):
     o = make_oracle(w, QT)
     rg = t.track(w["frames"][0], w["iters"])
     ro = o.track(w["frames"][0], w["iters"])
-    _assert_frame(rg, ro, f"quadtree {kind} frame 1", _oracle_spread(w, ro))
+    _assert_frame(w, rg, ro, f"quadtree {kind} frame 1")
     # inverse-depth variance of the final belief: r^2 var(ell), so it follows
     # the depth agreement (a handful of ill-conditioned pixels aside)
     ev = np.abs(rg["inv_depth_var"].astype(np.float64) - ro["inv_depth_var"]) / ro["inv_depth_var"]
@@ -176,4 +152,4 @@ def test_vga_frame_1():
     o = make_oracle(w, QT)
     rg = t.track(w["frames"][0], w["iters"])
     ro = o.track(w["frames"][0], w["iters"])
-    _assert_frame(rg, ro, "quadtree vga frame 1", _oracle_spread(w, ro))
+    _assert_frame(w, rg, ro, "quadtree vga frame 1")

@@ -406,13 +406,28 @@ __device__ inline void sample3(const Inputs& in, const Geo& g, double x, double 
 
 constexpr double WARP_EPS = 1e-3;
 
+// per-pixel inputs of the unary factors: keyframe intensity, photometric sigma
+// (when a map is bound) and log-depth prior mean (when a map is bound)
+struct PixelInputs {
+    float Is, sigD, prior_ell;
+};
+
+__device__ inline PixelInputs load_pixel_inputs(const Geo& g, const Strengths& s, const Inputs& in, int u, int v) {
+    const long pix = (long)v * g.pitch + u;
+    PixelInputs r;
+    r.Is = in.Is[pix];
+    r.sigD = s.has_sigma_map ? in.sigD[pix] : 0.0f;
+    r.prior_ell = s.has_prior_map ? in.prior_ell[pix] : 0.0f;
+    return r;
+}
+
 // Adds the photometric factor of pixel (u, v) (Eq. distrb_photo, warp of
 // Eq. warp, Huber covariance weighting) and the prior factor (Eq. prior) at
 // the linearisation point (R, t) = Exp(tau), ell to (L, eta). Returns the
 // valid-warp flag.
 __device__ inline bool unary_factors(const Geo& g, const Strengths& s, const Inputs& in, int u, int v,
                                      const double tau[6], const double R[9], const double t[3],
-                                     double ell, double L[28], double eta[7]) {
+                                     double ell, const PixelInputs& pin, double L[28], double eta[7]) {
 #pragma unroll
     for (int k = 0; k < 28; ++k) L[k] = 0.0;
 #pragma unroll
@@ -434,8 +449,7 @@ __device__ inline bool unary_factors(const Geo& g, const Strengths& s, const Inp
             const double y = fmin(fmax(wy, 0.0), (double)(g.H - 1));
             double It, gx, gy;
             sample3(in, g, x, y, It, gx, gy);
-            const long pix = (long)v * g.pitch + u;
-            const double r = (double)in.Is[pix] - It;
+            const double r = (double)pin.Is - It;
             // c = -g^T dw/da  (row 3-vector)
             const double c0 = -gx * g.fx * iz, c1 = -gy * g.fy * iz;
             const double c2 = (gx * g.fx * a0 + gy * g.fy * a1) * iz * iz;
@@ -453,7 +467,7 @@ __device__ inline bool unary_factors(const Geo& g, const Strengths& s, const Inp
             J[4] = rho * b1;
             J[5] = rho * b2;
             J[6] = -rho * (c0 * t[0] + c1 * t[1] + c2 * t[2]);
-            const double isig = s.has_sigma_map ? rcp_nr((double)in.sigD[pix]) : s.inv_sigD;
+            const double isig = s.has_sigma_map ? rcp_nr((double)pin.sigD) : s.inv_sigD;
             const double lamD = isig * isig;
             const double M = fabs(r) * isig;
             double kappa = 1.0;
@@ -528,10 +542,16 @@ __device__ inline bool unary_factors(const Geo& g, const Strengths& s, const Inp
             L[s7(a, b)] += lamP * g;
         }
     }
-    const double pell = s.has_prior_map ? (double)in.prior_ell[(long)v * g.pitch + u] : s.prior_ell;
+    const double pell = s.has_prior_map ? (double)pin.prior_ell : s.prior_ell;
     eta[6] -= lamP * (ell - pell);
     L[s7(6, 6)] += lamP;
     return valid;
+}
+
+__device__ inline bool unary_factors(const Geo& g, const Strengths& s, const Inputs& in, int u, int v,
+                                     const double tau[6], const double R[9], const double t[3],
+                                     double ell, double L[28], double eta[7]) {
+    return unary_factors(g, s, in, u, v, tau, R, t, ell, load_pixel_inputs(g, s, in, u, v), L, eta);
 }
 
 // ---------------------------------------------------------------------------

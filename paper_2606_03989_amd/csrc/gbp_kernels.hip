@@ -479,6 +479,160 @@ __device__ __attribute__((always_inline)) inline void iterate_pixel(const Geo& g
     if (!ok) atomicOr(health, 1);
 }
 
+// ---------------------------------------------------------------------------
+// fused pass with its loads issued together
+//
+// With one wave per SIMD (the pass keeps ~450 registers live) nothing hides
+// memory latency, so the number of dependent round trips to memory sets the
+// pass time. Every load whose address does not depend on computed values
+// (own point, the four neighbours' points, the four partials and normal
+// partials in flight, the normal targets, the keyframe intensity and the
+// optional sigma and prior maps) is issued at once at the start; a missing
+// neighbour's loads read the pixel itself and are discarded. What remains
+// dependent are the bilinear samples at the two warps. The arithmetic and its
+// order are those of iterate_pixel.
+
+// preloaded normal targets of the four edges: c of the left/upper pixel a
+struct EdgeTargets {
+    float c[4];
+};
+
+// normal_residual with a preloaded target
+__device__ inline bool normal_residual_c(float c, int d, double ell_i, double ell_j, double& r_recv) {
+    if (!isfinite(c)) return false;
+    const bool recv_is_b = (d == DIR_L || d == DIR_U);
+    r_recv = recv_is_b ? (ell_i - ell_j + (double)c) : (ell_i - ell_j - (double)c);
+    return true;
+}
+
+template <bool FINAL>
+__device__ __attribute__((always_inline)) inline void iterate_pixel_pf(
+    const Geo& g, const Strengths& s, const Inputs& in, const float* __restrict__ X, float* __restrict__ Y,
+    float* __restrict__ var_ll, float* __restrict__ valid, int* __restrict__ health, int u, int v) {
+    const long p = pix_of(g, u, v);
+    bool has[4];
+    long pn[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        int nu, nv;
+        has[d] = neighbour(g, u, v, d, nu, nv);
+        pn[d] = has[d] ? pix_of(g, nu, nv) : p;
+    }
+    // --- loads with computable addresses, all issued before any use
+    float pt[7], npt[4][7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) pt[k] = X[(long)(P_TAU + k) * g.plane + p];
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+#pragma unroll
+        for (int k = 0; k < 7; ++k) npt[d][k] = X[(long)(P_TAU + k) * g.plane + pn[d]];
+    float mid[4][27], mn[4][2];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+#pragma unroll
+        for (int k = 0; k < 27; ++k) mid[d][k] = X[(long)(P_MID + d * MID_STRIDE + k) * g.plane + p];
+        mn[d][0] = X[(long)(P_MN + 2 * d) * g.plane + p];
+        mn[d][1] = X[(long)(P_MN + 2 * d + 1) * g.plane + p];
+    }
+    EdgeTargets ct;
+    ct.c[DIR_L] = in.cxt[pn[DIR_L]];
+    ct.c[DIR_R] = in.cxt[p];
+    ct.c[DIR_U] = in.cyt[pn[DIR_U]];
+    ct.c[DIR_D] = in.cyt[p];
+    const PixelInputs pin = load_pixel_inputs(g, s, in, u, v);
+
+    // --- linearise at the current point
+    double tau[6], ell, R[9], t[3], L[28], eta[7];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) tau[k] = (double)pt[k];
+    ell = (double)pt[6];
+    se3_exp(tau, R, t);
+    const bool val = unary_factors(g, s, in, u, v, tau, R, t, ell, pin, L, eta);
+
+    // --- complete the partials in flight (complete_partials)
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        if (!has[d]) {
+#pragma unroll
+            for (int k = 0; k < 27; ++k) mid[d][k] = 0.0f;
+            mn[d][0] = mn[d][1] = 0.0f;
+            continue;
+        }
+        double tj[6], Rj[9], trj[3], r[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) tj[k] = (double)npt[d][k];
+        const double ellj = (double)npt[d][6];
+        se3_exp(tj, Rj, trj);
+        se3_between(Rj, trj, R, t, r);
+        double e6[6];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+            double e = (double)mid[d][a];
+#pragma unroll
+            for (int b = 0; b < 6; ++b) e -= (double)mid[d][6 + s6(a, b)] * r[b];
+            e6[a] = e;
+        }
+        double ne = 0.0;
+        float nl = 0.0f;
+        double rn;
+        if (s.lamN > 0.0 && normal_residual_c(ct.c[d], d, ell, ellj, rn)) {
+            nl = mn[d][1];
+            ne = (double)mn[d][0] - (double)nl * rn;
+        }
+        float lam[21];
+#pragma unroll
+        for (int k = 0; k < 21; ++k) lam[k] = mid[d][6 + k];
+        accumulate_message(L, eta, e6, lam, ne, nl, mid[d], mn[d]);
+    }
+
+    // --- update, relinearise, transport
+    double var;
+    bool ok = update_and_transport(L, eta, tau, ell, mid, mn, var);
+    round_point(tau, ell);
+    store_point(Y, g, p, tau, ell);
+    if (FINAL) {
+        store_messages(Y, g, p, mid, mn);
+        var_ll[p] = (float)var;
+        valid[p] = val ? 1.0f : 0.0f;
+    } else {
+        // --- linearise at the new point and send the next partials (emit_partials)
+        se3_exp(tau, R, t);
+        unary_factors(g, s, in, u, v, tau, R, t, ell, pin, L, eta);
+        add_messages(L, eta, mid, mn);
+        double P[21], pm[6], D, dv;
+        pose_marginal(L, eta, P, pm);
+        ok = depth_marginal(L, eta, D, dv) && ok;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            if (!has[d]) continue;
+            const long pj = pn[d];
+            const int slot = opposite(d);
+            double V[21], vv[6], Lp[21], h[6];
+#pragma unroll
+            for (int k = 0; k < 21; ++k) V[k] = P[k] - (double)mid[d][6 + k];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) vv[k] = pm[k] - (double)mid[d][k];
+            ok = identity_partial(s.lamR, V, vv, Lp, h) && ok;
+            float* dst = Y + (long)(P_MID + slot * MID_STRIDE) * g.plane + pj;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) dst[k * g.plane] = (float)h[k];
+#pragma unroll
+            for (int k = 0; k < 21; ++k) dst[(6 + k) * g.plane] = (float)Lp[k];
+            float* dn = Y + (long)(P_MN + 2 * slot) * g.plane + pj;
+            if (isfinite(ct.c[d]) && s.lamN > 0.0) {
+                double lp, hn;
+                normal_partial(s.lamN, D - (double)mn[d][1], dv - (double)mn[d][0], lp, hn);
+                dn[0] = (float)hn;
+                dn[g.plane] = (float)lp;
+            } else {
+                dn[0] = 0.0f;
+                dn[g.plane] = 0.0f;
+            }
+        }
+    }
+    if (!ok) atomicOr(health, 1);
+}
+
 __global__ __launch_bounds__(256) void k_fu_prologue(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
                                                      float* __restrict__ Y, int* __restrict__ health) {
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
@@ -494,7 +648,7 @@ __global__ __launch_bounds__(256) void k_fu_iterate(Geo g, Strengths s, Inputs i
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
     const int v = blockIdx.y * blockDim.y + threadIdx.y;
     if (u >= g.W || v >= g.H) return;
-    iterate_pixel<FINAL>(g, s, in, X, Y, var_ll, valid, health, u, v);
+    iterate_pixel_pf<FINAL>(g, s, in, X, Y, var_ll, valid, health, u, v);
 }
 
 // the same passes for the reverse sweep's recompute: the prologue also writes
@@ -654,7 +808,7 @@ __global__ __launch_bounds__(256) void k_batch_iterate(const SeqDesc* __restrict
     if (!batch_pixel(seqs, work, d, u, v, item)) return;
     const float* X = parity ? d->X1 : d->X0;
     float* Y = parity ? d->X0 : d->X1;
-    iterate_pixel<FINAL>(d->g, s, d->in, X, Y, d->var_ll, d->valid, health, u, v);
+    iterate_pixel_pf<FINAL>(d->g, s, d->in, X, Y, d->var_ll, d->valid, health, u, v);
 }
 
 // per work item: sum of the six pose planes, valid count, non-finite count of

@@ -174,6 +174,19 @@ int pixvod_set_keyframe(pixvod_ctx* ctx, const float* img, const float* normals,
  * PIXVOD_ESTATE before a tracked frame. */
 int pixvod_set_keyframe_transfer(pixvod_ctx* ctx, const float* img, const float* normals, int where);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * re-anchoring with depth transfer as pixvod_set_keyframe_transfer, with the
+ * same arguments and results, but its z-buffer is a static device array of
+ * 2^21 entries that each GPU holds for the lifetime of the process instead of
+ * a plane allocated on first use; nothing is allocated, and with device
+ * pointers (PIXVOD_DEVICE) nothing is copied through the host either.
+ * PIXVOD_EINVAL when H times the row pitch (W rounded up to a multiple of 64)
+ * exceeds 2^21 (1920 x 1080 fits); PIXVOD_ESTATE before a tracked frame.
+ * Every context on a GPU shares that GPU's array: calls on one GPU that
+ * overlap in time (different streams or threads) race. */
+int pixvod_set_keyframe_transfer_noalloc(pixvod_ctx* ctx, const float* img, const float* normals, int where);
+
 /* Optional per-pixel photometric sigma map (H*W); NULL restores the constant
  * params.sigma_D. */
 int pixvod_set_sigma_map(pixvod_ctx* ctx, const float* sigma_D_map, int where);

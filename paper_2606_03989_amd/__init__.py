@@ -78,6 +78,7 @@ _SIGNATURES = {
     "pixvod_set_keyframe": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "pixvod_set_sigma_map": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "pixvod_set_keyframe_transfer": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "pixvod_set_keyframe_transfer_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "pixvod_track": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.POINTER(TrackOut)]),
     "pixvod_iterate": (C.c_int, [C.c_void_p, C.c_int]),
     "pixvod_set_prior": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
@@ -234,14 +235,20 @@ class Tracker(_FollowsTorchStream):
     def set_schedule(self, schedule: int):
         _check(lib().pixvod_set_schedule(self._h, int(schedule)), self._h)
 
-    def set_keyframe(self, img, normals, transfer_depth: bool = False):
+    def set_keyframe(self, img, normals, transfer_depth: bool = False, noalloc: bool = False):
         """New keyframe; with transfer_depth the log-depths are first
-        forward-warped into it (img should be the frame just tracked)."""
+        forward-warped into it (img should be the frame just tracked);
+        noalloc selects the transfer's allocation-free entry point."""
         pi, wi, ki = _ptr(img)
         pn, wn, kn = _ptr(normals)
         if wi != wn:
             raise ValueError("image and normals must live in the same memory")
-        f = lib().pixvod_set_keyframe_transfer if transfer_depth else lib().pixvod_set_keyframe
+        if noalloc and not transfer_depth:
+            raise ValueError("noalloc applies to the depth-transfer re-anchoring")
+        if transfer_depth:
+            f = lib().pixvod_set_keyframe_transfer_noalloc if noalloc else lib().pixvod_set_keyframe_transfer
+        else:
+            f = lib().pixvod_set_keyframe
         self._follow_torch(wi)
         _check(f(self._h, C.c_void_p(pi), C.c_void_p(pn), wi), self._h)
 

@@ -10,6 +10,8 @@
 #include "gbp_transfer.h"
 #include "gbp_device.hpp"
 
+#include <mutex>
+
 namespace pv {
 
 namespace {
@@ -48,7 +50,36 @@ __global__ void k_tf_gather(Geo g, const unsigned* __restrict__ zb, float* __res
     if (b != kInfBits) X[(long)P_ELL * g.plane + pi] = (float)log((double)__uint_as_float(b));
 }
 
+std::mutex g_scratch_mutex;
+unsigned* g_scratch_ptr[kMaxDevices] = {};
+
 }  // namespace
+
+// z-buffer of the allocation-free re-anchoring entry point: each device holds
+// its own copy for the process's lifetime, shared by every call on it. Host
+// code uses the address looked up by transfer_scratch_init, never the name.
+static __device__ __align__(256) unsigned scratch[kTransferScratchMax];
+
+hipError_t transfer_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<unsigned*>(ptr);
+    return hipSuccess;
+}
+
+unsigned* transfer_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    return g_scratch_ptr[device];
+}
 
 hipError_t launch_depth_transfer(const Geo& g, const Pose& p, float* X, unsigned* zbuf, hipStream_t st) {
     const dim3 b(64, 4), gr((g.W + 63) / 64, (g.H + 3) / 4);

@@ -348,6 +348,10 @@ int pixvod_create(int H, int W, const pixvod_intrinsics* K, const pixvod_params*
     c->K = *K;
     c->P = P;
     c->device = dev;
+    if (transfer_scratch_init(dev) != hipSuccess) {
+        delete c;
+        return fail(nullptr, PIXVOD_EHIP, "hipGetSymbolAddress of the static z-buffer failed");
+    }
     c->schedule = (P.damping != 0.0f) ? PIXVOD_SCHED_PER_FACTOR : PIXVOD_SCHED_FUSED;
     std::memset(c->T_w_kf, 0, sizeof(c->T_w_kf));
     for (int k = 0; k < 4; ++k) c->T_w_kf[k * 5] = 1.0;
@@ -531,6 +535,26 @@ int pixvod_set_keyframe_transfer(pixvod_ctx* c, const float* img, const float* n
         p.t[r] = T[r * 4 + 3];
     }
     HIP_TRY(c, launch_depth_transfer(geo_of(c), p, c->X[c->cur], c->zbuf, c->stream));
+    return pixvod_set_keyframe(c, img, normals, where);
+}
+
+int pixvod_set_keyframe_transfer_noalloc(pixvod_ctx* c, const float* img, const float* normals, int where) {
+    if (!c) return fail(nullptr, PIXVOD_EINVAL, "ctx is NULL");
+    if (!img || !normals) return fail(c, PIXVOD_EINVAL, "img and normals are required");
+    if (where != PIXVOD_HOST && where != PIXVOD_DEVICE) return fail(c, PIXVOD_EINVAL, "bad location");
+    if (!c->have_track) return fail(c, PIXVOD_ESTATE, "no tracked frame since the keyframe");
+    if (c->plane > kTransferScratchMax)
+        return fail(c, PIXVOD_EINVAL, "frame too large for the static z-buffer (H * pitch > 2^21)");
+    unsigned* zb = transfer_scratch(c->device);
+    if (!zb) return fail(c, PIXVOD_ESTATE, "static z-buffer not set up on this device");
+    double T[16];
+    host_se3_exp(c->xi_last, T);
+    Pose p;
+    for (int r = 0; r < 3; ++r) {
+        for (int k = 0; k < 3; ++k) p.R[r * 3 + k] = T[r * 4 + k];
+        p.t[r] = T[r * 4 + 3];
+    }
+    HIP_TRY(c, launch_depth_transfer(geo_of(c), p, c->X[c->cur], zb, c->stream));
     return pixvod_set_keyframe(c, img, normals, where);
 }
 

@@ -389,20 +389,69 @@ def run_adjoint(n_frames: int, iters: int, ckpt: int, reps: int):
                 ratio_vs_plain=round(v_fa / v_plain, 4), gradients="sigma_D map, sigma_N, huber_k")
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(iters: int):
-    """The FP64 oracle on the first frame of the same workload, `iters` iterations."""
+    """The FP64 oracle, as it stands, timed on the host's cores: all threads
+    on the 32x24 pair in full (50 iterations), the 256x256 sequence's first 5
+    frames (20 iterations each) and the 640x480 frame 1 (`iters` iterations);
+    one thread on the 32x24 pair and 2 iterations of the 640x480 frame 1.
+    `value` is the 640x480 sample on all threads (the metric's workload);
+    about 15 s of CPU work on a 16-thread host."""
     import oracle
-    cam, I0, N0, frames, _ = vga_inputs(1)
-    cfg = oracle.config_for_camera(cam, **VGA_PARAMS)
-    o = oracle.Oracle(cfg)
-    o.set_keyframe(I0, N0)
-    a = time.perf_counter()
-    o.track(frames[0], iters)
-    b = time.perf_counter()
-    v = cam.H * cam.W * iters / (b - a) / 1e6
-    log(f"oracle: {b - a:.1f} s for {iters} iterations of 640x480 -> {v:.3f} Mpx-iter/s on {oracle.threads()} threads")
-    return dict(value=round(v, 4), unit="Mpixel-iter/s", cores=oracle.threads(), kind="oracle",
-                sample=f"frame 1 of the 640x480 sequence, {iters} GBP iterations ({b - a:.1f} s)")
+    from synth.scenes import SEQUENCE_CONFIGS, make_sequence_scene, render_sequence_frame, sequence_poses
+    import synth
+
+    def timed(cam, I0, N0, frames, n_it, kw):
+        o = oracle.Oracle(oracle.config_for_camera(cam, **kw))
+        o.set_keyframe(I0, N0)
+        a = time.perf_counter()
+        for f in frames:
+            o.track(f, n_it)
+        dt = time.perf_counter() - a
+        o.close()
+        return cam.H * cam.W * n_it * len(frames) / dt / 1e6, dt
+
+    all_threads = oracle.threads()
+    p = synth.tiny_pair(0)
+    tiny = (p["cam"], p["I_s"], p["normals_s"], [p["I_t"]], 50, dict(init_inv_depth=0.3))
+    cfg = SEQUENCE_CONFIGS["ppa256"]
+    scene, cam2 = make_sequence_scene(cfg)
+    poses = sequence_poses(cfg)
+    I2, _, N2, _ = render_sequence_frame(cfg, scene, cam2, poses, 0, keyframe=True)
+    fr2 = [render_sequence_frame(cfg, scene, cam2, poses, f)[0] for f in range(1, 6)]
+    ppa = (cam2, I2, N2, fr2, 20, dict(sigma_P=0.01, huber_k=400.0))
+    cam3, I3, N3, fr3, _ = vga_inputs(1)
+    samples = {}
+    for name, wl in (("tiny 32x24, 50 iterations", tiny), ("256x256, frames 1-5 x 20 iterations", ppa),
+                     (f"640x480, frame 1 x {iters} iterations", (cam3, I3, N3, fr3, iters, VGA_PARAMS))):
+        v, dt = timed(*wl)
+        samples[name] = dict(Mpx_iter_s=round(v, 4), seconds=round(dt, 2), threads=all_threads)
+        if name.startswith("640x480"):
+            value, vdt = v, dt
+    oracle.set_threads(1)
+    try:
+        for name, wl in (("tiny 32x24, 50 iterations", tiny),
+                         ("640x480, frame 1 x 2 iterations", (cam3, I3, N3, fr3, 2, VGA_PARAMS))):
+            v, dt = timed(*wl)
+            samples[name + ", 1 thread"] = dict(Mpx_iter_s=round(v, 4), seconds=round(dt, 2), threads=1)
+    finally:
+        oracle.set_threads(all_threads)
+    cpu = _cpu_model()
+    log(f"oracle on {all_threads} threads of {cpu}: " +
+        "; ".join(f"{k}: {d['Mpx_iter_s']} Mpx-iter/s ({d['seconds']} s)" for k, d in samples.items()))
+    return dict(value=round(value, 4), unit="Mpixel-iter/s", cores=all_threads, kind="oracle",
+                sample=f"frame 1 of the 640x480 sequence, {iters} GBP iterations ({vdt:.1f} s), all threads",
+                cpu_model=cpu, samples=samples)
 
 
 def noise_sweep(n_frames: int = 20, iters: int = 20):
@@ -712,7 +761,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--per-factor-steps", type=int, default=3)
-    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--probe", action="store_true", help="short run for hardware counters; no JSON line")
     ap.add_argument("--noise-sweep", action="store_true",
@@ -767,6 +816,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
+        "storage_dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "vga640x480 piecewise-planar sequence, 20 GBP iterations per frame, fused schedule",
                    "H": g["H"], "W": g["W"], "iters_per_frame": g["iters"], "state": "fp32 SoA, 123 planes",

@@ -101,6 +101,7 @@ def load(path: str) -> C.CDLL:
     L.or_unary.argtypes = [C.c_void_p, C.c_int, C.c_int, dp, dp, C.POINTER(C.c_int)]
     L.or_factor_message.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, dp]
     L.or_threads.restype = C.c_int
+    L.or_set_threads.argtypes = [C.c_int]
     return L
 
 
@@ -346,3 +347,8 @@ class Oracle:
 
 def threads() -> int:
     return lib().or_threads()
+
+
+def set_threads(n: int):
+    """Threads of the oracle's OpenMP loops from now on."""
+    lib().or_set_threads(int(n))

@@ -507,6 +507,16 @@ int or_threads(void) {
 #endif
 }
 
+/* threads of the OpenMP loops from now on (n >= 1); the CPU-baseline timing
+ * runs one thread and all host threads in one process */
+void or_set_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 or_ctx* or_create(const or_config* cfg) {
     if (!cfg || cfg->H < 1 || cfg->W < 2 || !(cfg->fx > 0) || !(cfg->fy > 0)) return NULL;
     if (cfg->topology != OR_TOPO_GRID && cfg->topology != OR_TOPO_QUADTREE) return NULL;

@@ -88,6 +88,7 @@ void or_default_config(or_config* cfg);
 or_ctx* or_create(const or_config* cfg);
 void or_destroy(or_ctx* ctx);
 int or_threads(void);
+void or_set_threads(int n);
 
 /* per-pixel sigma_D map (H*W); NULL restores the constant cfg.sigma_D */
 int or_set_sigma_D_map(or_ctx* ctx, const double* sigma_map);

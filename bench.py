@@ -245,49 +245,138 @@ def _render_seq(args):
     return cam, I0, np.ascontiguousarray(N0), frames
 
 
+# anonymous shared mappings (one per sequence) that the forked render workers
+# fill: frames 1..n, then their normal maps
+_SHARED = {}
+
+
+def _render_seq_shared(args):
+    """Renders sequence s's keyframe and target frames 1..n_frames with their
+    normal maps into the anonymous shared mapping _SHARED[s] (created by the
+    parent before the workers fork); returns the keyframe."""
+    s, n_frames = args
+    import numpy as np
+    from synth.scenes import batch_sequence_config, make_sequence_scene, render_sequence_frame, sequence_poses
+    cfg = batch_sequence_config(s)
+    scene, cam = make_sequence_scene(cfg)
+    poses = sequence_poses(cfg)
+    I0, _, N0, _ = render_sequence_frame(cfg, scene, cam, poses, 0, keyframe=True)
+    buf = _SHARED[s]
+    n = cam.H * cam.W
+    fr = np.ndarray((n_frames, cam.H, cam.W), np.float32, buffer=buf, offset=0)
+    nm = np.ndarray((n_frames, cam.H, cam.W, 3), np.float32, buffer=buf, offset=4 * n_frames * n)
+    for f in range(n_frames):
+        img, _, nrm, _ = render_sequence_frame(cfg, scene, cam, poses, f + 1)
+        fr[f] = img
+        nm[f] = nrm
+    del fr, nm
+    return cam, I0, np.ascontiguousarray(N0, dtype=np.float32)
+
+
 BATCH_PARAMS = dict(sigma_P=0.01, huber_k=400.0)
 
 
-def run_batch(n_seq: int, steps: int, iters: int, plain_steps: int):
-    """64 seeded sequences, resolutions cycling 128x96, 256x256, 320x240,
-    640x480; each step advances every sequence by one frame (`iters`
-    iterations). The batch runs one launch per pass over all sequences with a
-    graph-captured frame step and an autotuned tile; the plain leg runs the
-    same sequences one after another in per-sequence contexts."""
+def run_batch(n_seq: int, n_frames: int, iters: int, plain_steps: int, persistent_steps: int = 8,
+              kf_frames: int = 16):
+    """64 seeded 50-frame sequences, resolutions cycling 128x96, 256x256,
+    320x240, 640x480; frames 1..n_frames are tracked after keyframe 0; each
+    step advances every sequence by one distinct frame
+    (`iters` iterations) with the keyframe test and re-anchoring on the device
+    inside the step. Frames 1 and 2 warm up (graph capture, tile autotuning);
+    frames 3..n_frames are timed. The batch runs one launch per pass over all
+    sequences in a graph-captured frame step; the persistent variant (one
+    cooperative launch per iteration block) is timed on frames 3.. in a second
+    batch; the plain leg runs the same sequences one after another in
+    per-sequence contexts. Keyframes are re-anchored every `kf_frames`
+    frames (the paper's 150 exceeds a 50-frame sequence), so the timed steps
+    include the device-side re-anchoring."""
+    import mmap
     import multiprocessing as mp
+    import numpy as np
     import torch
     import paper_2606_03989_amd as pv
-    n_frames = 3
-    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
-        data = pool.map(_render_seq, [(s, n_frames) for s in range(n_seq)])
+    from synth.scenes import batch_resolution
+    from synth.scenes import batch_sequence_config
     dev = torch.device("cuda:0")
+    n_max = batch_sequence_config(0).n_frames - 1
+    if not 2 < n_frames <= n_max:
+        raise SystemExit(f"--batch-frames must be in 3..{n_max} (frames after the keyframe)")
+    shapes = [batch_resolution(s) for s in range(n_seq)]
+    for s, (H, W) in enumerate(shapes):
+        _SHARED[s] = mmap.mmap(-1, 16 * n_frames * H * W)
+    try:
+        with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+            data = pool.map(_render_seq_shared, [(s, n_frames) for s in range(n_seq)])
+        fr, nm = [], []
+        for s, (H, W) in enumerate(shapes):
+            a = np.ndarray((n_frames, H, W), np.float32, buffer=_SHARED[s], offset=0)
+            b_ = np.ndarray((n_frames, H, W, 3), np.float32, buffer=_SHARED[s], offset=4 * n_frames * H * W)
+            fr.append([f for f in torch.from_numpy(a.copy()).to(dev)])
+            nm.append([x for x in torch.from_numpy(b_.copy()).to(dev)])
+            del a, b_
+    finally:
+        for s in list(_SHARED):
+            _SHARED.pop(s).close()
     cams = [d[0] for d in data]
-    shapes = [(c.H, c.W) for c in cams]
     Ks = [(c.fx, c.fy, c.cx, c.cy) for c in cams]
     kf = [torch.from_numpy(d[1]).to(dev) for d in data]
     kn = [torch.from_numpy(d[2]).to(dev) for d in data]
-    fr = [[torch.from_numpy(f).to(dev) for f in d[3]] for d in data]
     px = sum(h * w for h, w in shapes)
     stream = torch.cuda.current_stream()
 
-    b = pv.Batch(shapes, Ks, **BATCH_PARAMS)
-    b.set_stream(stream)
-    b.set_keyframes(list(range(n_seq)), kf, kn)
-    b.track([f[0] for f in fr], iters)                         # warm-up, graph capture
+    def make(persistent):
+        b = pv.Batch(shapes, Ks, kf_max_frames=kf_frames, **BATCH_PARAMS)
+        b.set_stream(stream)
+        b.set_persistent(persistent)
+        b.set_keyframes(list(range(n_seq)), kf, kn)
+        return b
+
+    def step(b, f):
+        return b.track([x[f] for x in fr], iters, normals=[x[f] for x in nm])
+
+    b = make(False)
+    step(b, 0)                                         # warm-up, graph capture
     tx, ty = b.autotune(iters)
-    b.track([f[1] for f in fr], iters)
+    step(b, 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    step_ms = []
-    for k in range(steps):
-        b.track([f[k % n_frames] for f in fr], iters)
+    step_ms, flags, reanchored = [], 0, 0
+    for f in range(2, n_frames):
+        r = step(b, f)
         step_ms.append(b.last_step_ms())
+        for o in r:
+            flags |= o["flags"]
+            reanchored += 1 if o["flags"] & pv.KEYFRAME_DUE else 0
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
+    steps = n_frames - 2
     batch_value = px * iters * steps / tb / 1e6
     b.close()
-    log(f"batched: {n_seq} sequences, {px} px, tile {tx}x{ty}: {tb * 1e3 / steps:.2f} ms/step "
-        f"(graph {sum(step_ms) / len(step_ms):.2f} ms) -> {batch_value:.1f} Mpx-iter/s")
+    log(f"batched: {n_seq} sequences, {px} px, frames 3-{n_frames}, tile {tx}x{ty}: {tb * 1e3 / steps:.2f} ms/step "
+        f"(graph {sum(step_ms) / len(step_ms):.2f} ms) -> {batch_value:.1f} Mpx-iter/s; flags seen {flags}, "
+        f"{reanchored} re-anchorings")
+
+    persistent = None
+    if persistent_steps > 0:
+        bp = make(True)
+        bp.set_tile(tx, ty)
+        step(bp, 0)
+        step(bp, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ns = min(persistent_steps, n_frames - 2)
+        pms = []
+        for f in range(2, 2 + ns):
+            step(bp, f)
+            pms.append(bp.last_step_ms())
+        torch.cuda.synchronize()
+        tpp = time.perf_counter() - t0
+        bp.close()
+        persistent = dict(value=round(px * iters * ns / tpp / 1e6, 1), ms_per_step=round(tpp * 1e3 / ns, 3),
+                          step_event_ms=round(sum(pms) / len(pms), 3), steps=ns,
+                          launch_per_pass_step_event_ms=round(sum(step_ms[:ns]) / ns, 3))
+        log(f"batched, persistent iteration block: {tpp * 1e3 / ns:.2f} ms/step (events {sum(pms) / len(pms):.2f} ms) "
+            f"against {sum(step_ms[:ns]) / ns:.2f} ms with one launch per pass on the same frames")
 
     plain = []
     for s in range(n_seq):
@@ -300,7 +389,7 @@ def run_batch(n_seq: int, steps: int, iters: int, plain_steps: int):
     t0 = time.perf_counter()
     for k in range(plain_steps):
         for s in range(n_seq):
-            plain[s].track(fr[s][k % n_frames], iters, maps=False)
+            plain[s].track(fr[s][1 + k], iters, maps=False)
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
     plain_value = px * iters * plain_steps / tp / 1e6
@@ -308,10 +397,13 @@ def run_batch(n_seq: int, steps: int, iters: int, plain_steps: int):
         t.close()
     log(f"plain per-sequence contexts: {tp * 1e3 / plain_steps:.2f} ms/step -> {plain_value:.1f} Mpx-iter/s")
     return dict(value=round(batch_value, 1), unit="Mpixel-iter/s", sequences=n_seq, pixels=px, iters_per_frame=iters,
-                steps=steps, ms_per_step=round(tb * 1e3 / steps, 3), tile=[tx, ty],
+                frames_per_sequence=n_frames + 1, tracked_frames=n_frames, steps=steps, ms_per_step=round(tb * 1e3 / steps, 3), tile=[tx, ty],
+                flags_seen=flags, reanchorings=reanchored, persistent=persistent,
                 plain_value=round(plain_value, 1), plain_ms_per_step=round(tp * 1e3 / plain_steps, 3),
                 speedup_vs_plain=round(batch_value / plain_value, 3),
-                resolutions="128x96, 256x256, 320x240, 640x480 (16 each)")
+                resolutions="128x96, 256x256, 320x240, 640x480 (16 each)",
+                reanchoring="keyframe test and re-anchoring on the device inside each captured frame step",
+                kf_max_frames=kf_frames)
 
 
 DIFF_PARAMS = dict(sigma_P=0.01, huber_k=10.0)
@@ -690,8 +782,9 @@ def pv_exp(xi):
 
 def probe(frames: int = 3, copy_mb: int = 512):
     """Short run for hardware-counter collection: the fused schedule on a few
-    frames, one per-factor frame, and a plain device copy of known size that
-    calibrates the byte counters."""
+    frames, one per-factor frame, the quadtree, a short forward+adjoint on the
+    320x240 differentiation sequence (2 frames x 10 iterations) and a plain
+    device copy of known size that calibrates the byte counters."""
     import torch
     import paper_2606_03989_amd as pv
     cam, I0, N0, fr, _ = vga_inputs(frames)
@@ -713,6 +806,7 @@ def probe(frames: int = 3, copy_mb: int = 512):
     for f in d_fr:
         t.track(f, 20, maps=False)
     t.close()
+    run_adjoint(2, 10, 5, 1)
     # calibration: a plain device copy of a source evicted from the last-level
     # cache by a larger fill in between, so every source byte comes from HBM
     n = copy_mb * (1 << 20) // 4
@@ -766,8 +860,12 @@ def main():
     ap.add_argument("--probe", action="store_true", help="short run for hardware counters; no JSON line")
     ap.add_argument("--noise-sweep", action="store_true",
                     help="tracking accuracy under sensor noise (clean, Gaussian, mild, strong); its own JSON line")
-    ap.add_argument("--batch-steps", type=int, default=4, help="timed frame steps of the 64-sequence batch (0: skip)")
+    ap.add_argument("--batch-frames", type=int, default=49,
+                    help="tracked frames per 50-frame sequence of the 64-sequence batch (at most 49: frame 0 is the "
+                         "keyframe); 2 warm up, the rest are timed (0: skip)")
     ap.add_argument("--batch-seqs", type=int, default=64)
+    ap.add_argument("--batch-kf-frames", type=int, default=16,
+                    help="frames per keyframe in the batch leg (re-anchoring inside the timed steps)")
     ap.add_argument("--no-quadtree", dest="quadtree", action="store_false",
                     help="skip the quadtree-topology leg on the same frames")
     ap.add_argument("--transfer-check", action="store_true",
@@ -801,7 +899,8 @@ def main():
     g = run_gpu(args)
     quadtree = run_quadtree(args, g) if args.quadtree else None
     central = run_central(args, g) if args.central else None
-    batched = run_batch(args.batch_seqs, args.batch_steps, 15, max(1, args.batch_steps // 2)) if args.batch_steps > 0 else None
+    batched = (run_batch(args.batch_seqs, args.batch_frames, 15, 2, kf_frames=args.batch_kf_frames)
+               if args.batch_frames > 2 else None)
     adjoint = run_adjoint(args.adjoint_frames, 30, 10, 2) if args.adjoint_frames > 0 else None
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_iters)
     out = {

@@ -275,6 +275,25 @@ int pixvod_batch_set_keyframes(pixvod_batch* b, int m, const int* seq_ids, const
 int pixvod_batch_track(pixvod_batch* b, const float* const* frames, int where, int n_iters,
                        pixvod_track_out* outs);
 
+/* As pixvod_batch_track, and inside the same frame step the keyframe test
+ * (Sec. 3.5) runs on the device: every sequence whose test fires on the frame
+ * just tracked is re-anchored on it by a kernel predicated on that sequence's
+ * device flag, as pixvod_set_keyframe would (the frame becomes the keyframe
+ * image, normals[i] (H[i]*W[i]*3, unit normals in that frame's camera) give
+ * the normal-integration targets, pose linearisation points and messages
+ * reset, log-depths kept, the keyframe's world pose becomes the frame's).
+ * outs[i].flags carries PIXVOD_KEYFRAME_DUE for the re-anchored sequences;
+ * the maps are those of the frame just tracked. Device frames and normals
+ * (PIXVOD_DEVICE) are read in place until the call returns. */
+int pixvod_batch_track_reanchor(pixvod_batch* b, const float* const* frames, const float* const* normals,
+                                int where, int n_iters, pixvod_track_out* outs);
+
+/* Runs the iteration block of each frame step (prologue and n_iters passes)
+ * as one persistent cooperative launch with a grid-wide barrier between the
+ * passes (enable = 1) instead of one captured launch per pass (0, default).
+ * Results are identical; the grid is the co-resident maximum for the tile. */
+int pixvod_batch_set_persistent(pixvod_batch* b, int enable);
+
 /* Tile shape of the work list (tile_x * tile_y <= 256, both >= 1). */
 int pixvod_batch_set_tile(pixvod_batch* b, int tile_x, int tile_y);
 

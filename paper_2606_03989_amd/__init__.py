@@ -95,6 +95,9 @@ _SIGNATURES = {
     "pixvod_batch_set_keyframes": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_void_p),
                                              C.POINTER(C.c_void_p), C.c_int]),
     "pixvod_batch_track": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_int, C.c_int, C.POINTER(TrackOut)]),
+    "pixvod_batch_track_reanchor": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int,
+                                              C.c_int, C.POINTER(TrackOut)]),
+    "pixvod_batch_set_persistent": (C.c_int, [C.c_void_p, C.c_int]),
     "pixvod_batch_set_tile": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "pixvod_batch_autotune": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "pixvod_batch_last_step_ms": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
@@ -407,6 +410,11 @@ class Batch(_FollowsTorchStream):
         _batch_check(lib().pixvod_batch_set_keyframes(self._h, m, ids, (C.c_void_p * m)(*pi), (C.c_void_p * m)(*pn),
                                                       HOST if where is None else where))
 
+    def set_persistent(self, enable: bool = True):
+        """Iteration block as one persistent cooperative launch (True) or one
+        captured launch per pass (False, default)."""
+        _batch_check(lib().pixvod_batch_set_persistent(self._h, 1 if enable else 0))
+
     def set_tile(self, tx: int, ty: int):
         _batch_check(lib().pixvod_batch_set_tile(self._h, int(tx), int(ty)))
 
@@ -420,7 +428,10 @@ class Batch(_FollowsTorchStream):
         _batch_check(lib().pixvod_batch_last_step_ms(self._h, C.byref(ms)))
         return ms.value
 
-    def track(self, frames, n_iters: int, maps: bool = False):
+    def track(self, frames, n_iters: int, maps: bool = False, normals=None):
+        """One frame per sequence; with `normals` (one normal map per frame)
+        sequences whose keyframe test fires are re-anchored on the frame just
+        tracked inside the same frame step."""
         keep, ptrs, where = [], [], None
         for f in frames:
             p, w, k = _ptr(f)
@@ -430,6 +441,15 @@ class Batch(_FollowsTorchStream):
                 raise ValueError("all frames must live in the same memory")
             keep.append(k)
             ptrs.append(p)
+        nptrs = None
+        if normals is not None:
+            nptrs = []
+            for nm in normals:
+                p, w, k = _ptr(nm)
+                if w != where:
+                    raise ValueError("frames and normals must live in the same memory")
+                keep.append(k)
+                nptrs.append(p)
         outs = (TrackOut * self.n)()
         maps_out = []
         for i, (H, W) in enumerate(self.shapes):
@@ -442,7 +462,11 @@ class Batch(_FollowsTorchStream):
             else:
                 maps_out.append((None, None))
         self._follow_torch(where)
-        _batch_check(lib().pixvod_batch_track(self._h, (C.c_void_p * self.n)(*ptrs), where, int(n_iters), outs))
+        if nptrs is None:
+            _batch_check(lib().pixvod_batch_track(self._h, (C.c_void_p * self.n)(*ptrs), where, int(n_iters), outs))
+        else:
+            _batch_check(lib().pixvod_batch_track_reanchor(self._h, (C.c_void_p * self.n)(*ptrs),
+                                                           (C.c_void_p * self.n)(*nptrs), where, int(n_iters), outs))
         return [dict(xi=np.array(o.xi_rel[:]), T_world=np.array(o.T_world[:]).reshape(4, 4),
                      valid_fraction=float(o.valid_fraction), frames_since_keyframe=int(o.frames_since_keyframe),
                      flags=int(o.flags), inv_depth=mo[0], inv_depth_var=mo[1])

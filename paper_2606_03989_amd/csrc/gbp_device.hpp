@@ -76,10 +76,14 @@ struct SeqDesc {
     float* X1;
     float* var_ll;
     float* valid;
-    const float* frame;   // staged dense target frame (H * W)
+    const float* frame;   // dense target frame (H * W) of the current step
+    const float* normals; // its normal map (H * W * 3), for re-anchoring on it
     float* It;            // frame-prep outputs (same planes as in.It, in.Gx, in.Gy)
     float* Gx;
     float* Gy;
+    float* Is;            // keyframe-prep outputs (same planes as in.Is, in.cxt, in.cyt)
+    float* cxt;
+    float* cyt;
     int tile_base;        // natural index of the sequence's first work item
     int tiles_x;          // tiles per image row
     int n_tiles;
@@ -98,6 +102,12 @@ struct BatchLaunch {
     int* health;
     double* partial;      // 8 doubles per work item
     double* result;       // 8 doubles per sequence
+    // keyframe test and re-anchoring on the device (Sec. 3.5)
+    int* fsk;             // per sequence: frames tracked since its keyframe
+    unsigned* flags;      // per sequence: flags of the frame just tracked
+    int kf_max_frames;
+    float kf_min_valid;
+    int reanchor;         // re-anchor due sequences on the frame just tracked
 };
 
 // ---------------------------------------------------------------------------

@@ -40,8 +40,19 @@ hipError_t launch_pack_state(const Geo& g, const float* X, float* dense, int to_
 hipError_t launch_copy_plane(const Geo& g, const float* dense, float* plane, hipStream_t st);
 
 // one frame step of a batch: clear health, frame prep, prologue, n passes,
-// per-sequence statistics (canonical state ends in buffer parity ^ (n > 0 ? (n + 1) & 1 : 0))
+// per-sequence statistics, keyframe test and re-anchoring (canonical state
+// ends in buffer parity ^ (n > 0 ? (n + 1) & 1 : 0))
 hipError_t launch_batch_frame_step(const BatchLaunch& b, int n_iters, hipStream_t st);
+// p[0 .. n) = value
+hipError_t launch_set_ints(int* p, int n, int value, hipStream_t st);
+// keyframe test of the frame just tracked and, if b.reanchor, re-anchoring of
+// the due sequences on it (canonical state in buffer `parity`)
+hipError_t launch_batch_keyframe(const BatchLaunch& b, int parity, hipStream_t st);
+// the same frame step with the iteration block as one persistent cooperative
+// launch of grid_blocks workgroups (batch_persistent_grid: the co-resident
+// maximum, a multiple of 8; 0 if it cannot be determined)
+int batch_persistent_grid(const BatchLaunch& b);
+hipError_t launch_batch_frame_step_persistent(const BatchLaunch& b, int n_iters, int grid_blocks, hipStream_t st);
 // bare passes (autotuning and timing)
 hipError_t launch_batch_passes(const BatchLaunch& b, int n_iters, bool prologue, bool final_last, hipStream_t st);
 

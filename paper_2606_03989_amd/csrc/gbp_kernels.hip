@@ -14,6 +14,10 @@
 #include "gbp_kernels.h"
 #include "gbp_device.hpp"
 
+#include <hip/hip_cooperative_groups.h>
+
+namespace cg = cooperative_groups;
+
 namespace pv {
 
 // belief mean, relinearisation (Eq. var) and first-order transport of the
@@ -236,12 +240,9 @@ __global__ void k_frame_prep(Geo g, const float* __restrict__ src, long src_pitc
 
 // keyframe image, normal-integration targets (row a2) and the state reset:
 // pose linearisation points to identity, messages to zero, log-depth kept
-__global__ void k_keyframe_prep(Geo g, const float* __restrict__ img, const float* __restrict__ normals,
-                                float* __restrict__ Is, float* __restrict__ cxt, float* __restrict__ cyt,
-                                float* __restrict__ X, float* __restrict__ X2) {
-    const int u = blockIdx.x * blockDim.x + threadIdx.x;
-    const int v = blockIdx.y * blockDim.y + threadIdx.y;
-    if (u >= g.W || v >= g.H) return;
+__device__ __attribute__((always_inline)) inline void keyframe_prep_pixel(
+    const Geo& g, const float* __restrict__ img, const float* __restrict__ normals, float* __restrict__ Is,
+    float* __restrict__ cxt, float* __restrict__ cyt, float* __restrict__ X, float* __restrict__ X2, int u, int v) {
     const long dense = (long)v * g.W + u;
     const long p = pix_of(g, u, v);
     Is[p] = img[dense];
@@ -259,6 +260,15 @@ __global__ void k_keyframe_prep(Geo g, const float* __restrict__ img, const floa
     }
     X[P_ELL * g.plane + p] = ell;
     X2[P_ELL * g.plane + p] = ell;
+}
+
+__global__ void k_keyframe_prep(Geo g, const float* __restrict__ img, const float* __restrict__ normals,
+                                float* __restrict__ Is, float* __restrict__ cxt, float* __restrict__ cyt,
+                                float* __restrict__ X, float* __restrict__ X2) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y * blockDim.y + threadIdx.y;
+    if (u >= g.W || v >= g.H) return;
+    keyframe_prep_pixel(g, img, normals, Is, cxt, cyt, X, X2, u, v);
 }
 
 __global__ void k_init_state(Geo g, float* __restrict__ X, float ell0) {
@@ -877,6 +887,76 @@ __global__ void k_clear_int(int* __restrict__ p) {
     if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = 0;
 }
 
+// keyframe test of the frame just tracked for every sequence (Sec. 3.5: frame
+// count and overlap), on the device: flags and the frame counter
+__global__ void k_batch_keyframe_test(const SeqDesc* __restrict__ seqs, int n_seq, const double* __restrict__ result,
+                                      const int* __restrict__ health, int* __restrict__ fsk,
+                                      unsigned* __restrict__ flags, int max_frames, float min_valid, int reanchor) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_seq) return;
+    const double inv_n = 1.0 / ((double)seqs[i].g.H * seqs[i].g.W);
+    const float vf = (float)(result[8 * i + 6] * inv_n);
+    const int count = fsk[i] + 1;
+    unsigned f = 0;
+    if (count >= max_frames || vf < min_valid) f |= 1u;          // keyframe due
+    if (vf < min_valid) f |= 4u;                                  // low overlap
+    if (result[8 * i + 7] > 0.0 || *health != 0) f |= 2u;         // diverged
+    flags[i] = f;
+    fsk[i] = (reanchor && (f & 1u)) ? 0 : count;
+}
+
+// re-anchoring on the frame just tracked, predicated on the device flag of
+// the tile's sequence: the frame becomes the keyframe image, its normals the
+// normal-integration targets; pose linearisation points and messages reset,
+// log-depths kept (the graph of a frame step has no branches)
+__global__ __launch_bounds__(256) void k_batch_keyframe_apply(const SeqDesc* __restrict__ seqs,
+                                                              const int2* __restrict__ work, int parity,
+                                                              const unsigned* __restrict__ flags) {
+    const SeqDesc* d;
+    int u, v, item;
+    const bool in_img = batch_pixel(seqs, work, d, u, v, item);
+    const int seq = work[blockIdx.x].y;
+    if (!in_img || !(flags[seq] & 1u)) return;
+    float* X = parity ? d->X1 : d->X0;
+    float* X2 = parity ? d->X0 : d->X1;
+    keyframe_prep_pixel(d->g, d->frame, d->normals, d->Is, d->cxt, d->cyt, X, X2, u, v);
+}
+
+__global__ void k_set_ints(int* __restrict__ p, int n, int value) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = value;
+}
+
+// the iteration block of a frame step in one launch: the n_passes non-final
+// passes that follow the prologue, with a grid-wide barrier between passes
+// (the prologue and the final pass, which writes the canonical messages, are
+// launches of their own). The grid is co-resident (cooperative launch) and a
+// multiple of 8 workgroups, so workgroup b, which runs items b, b + G,
+// b + 2G, ..., stays with the work list's range of its XCD. Every workgroup
+// reaches every barrier: pixels outside an image skip the arithmetic, not the
+// barrier.
+__global__ __launch_bounds__(256) void k_batch_persistent(const SeqDesc* __restrict__ seqs,
+                                                          const int2* __restrict__ work, int n_work, int parity,
+                                                          int n_passes, Strengths s, int* __restrict__ health) {
+    cg::grid_group grid = cg::this_grid();
+    for (int pass = 0; pass < n_passes; ++pass) {
+        const int par = parity ^ (pass & 1);
+        for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
+            const int2 wi = work[w];
+            const SeqDesc* d = &seqs[wi.y];
+            const int tile = wi.x - d->tile_base;
+            const int u = (tile % d->tiles_x) * (int)blockDim.x + (int)threadIdx.x;
+            const int v = (tile / d->tiles_x) * (int)blockDim.y + (int)threadIdx.y;
+            if (u < d->g.W && v < d->g.H) {
+                const float* X = par ? d->X1 : d->X0;
+                float* Y = par ? d->X0 : d->X1;
+                iterate_pixel_pf<false>(d->g, s, d->in, X, Y, d->var_ll, d->valid, health, u, v);
+            }
+        }
+        if (pass + 1 < n_passes) grid.sync();
+    }
+}
+
 hipError_t launch_batch_frame_step(const BatchLaunch& b, int n_iters, hipStream_t st) {
     const dim3 blk(b.tile_x, b.tile_y), grid(b.n_work);
     hipLaunchKernelGGL(k_clear_int, dim3(1), dim3(64), 0, st, b.health);
@@ -895,7 +975,59 @@ hipError_t launch_batch_frame_step(const BatchLaunch& b, int n_iters, hipStream_
     }
     hipLaunchKernelGGL(k_batch_stats, grid, blk, 0, st, b.seqs, b.work, parity, b.partial);
     hipLaunchKernelGGL(k_batch_final, dim3(b.n_seq), dim3(256), 0, st, b.seqs, b.partial, b.result);
+    return launch_batch_keyframe(b, parity, st);
+}
+
+hipError_t launch_set_ints(int* p, int n, int value, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_ints, dim3((n + 255) / 256), dim3(256), 0, st, p, n, value);
     return hipGetLastError();
+}
+
+hipError_t launch_batch_keyframe(const BatchLaunch& b, int parity, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_keyframe_test, dim3((b.n_seq + 63) / 64), dim3(64), 0, st, b.seqs, b.n_seq, b.result,
+                       b.health, b.fsk, b.flags, b.kf_max_frames, b.kf_min_valid, b.reanchor);
+    if (b.reanchor)
+        hipLaunchKernelGGL(k_batch_keyframe_apply, dim3(b.n_work), dim3(b.tile_x, b.tile_y), 0, st, b.seqs, b.work,
+                           parity, b.flags);
+    return hipGetLastError();
+}
+
+int batch_persistent_grid(const BatchLaunch& b) {
+    int per_cu = 0, dev = 0, n_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_batch_persistent),
+                                                     b.tile_x * b.tile_y, 0) != hipSuccess)
+        return 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    int g = per_cu * n_cu;
+    if (g > b.n_work) g = b.n_work;
+    if (g >= 8) g -= g % 8;
+    return g;
+}
+
+hipError_t launch_batch_frame_step_persistent(const BatchLaunch& b, int n_iters, int grid_blocks, hipStream_t st) {
+    const dim3 blk(b.tile_x, b.tile_y), grid(b.n_work);
+    hipLaunchKernelGGL(k_clear_int, dim3(1), dim3(64), 0, st, b.health);
+    hipLaunchKernelGGL(k_batch_frame_prep, grid, blk, 0, st, b.seqs, b.work);
+    hipLaunchKernelGGL(k_batch_prologue, grid, blk, 0, st, b.seqs, b.work, b.parity, b.s, b.health);
+    const SeqDesc* seqs = b.seqs;
+    const int2* work = b.work;
+    int n_work = b.n_work, parity = b.parity ^ 1, n_passes = n_iters - 1;
+    Strengths s = b.s;
+    int* health = b.health;
+    if (n_passes > 0) {
+        void* args[] = {&seqs, &work, &n_work, &parity, &n_passes, &s, &health};
+        hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_batch_persistent), dim3(grid_blocks),
+                                                  blk, args, 0, st);
+        if (e != hipSuccess) return e;
+    }
+    const int fin = b.parity ^ 1 ^ (n_passes & 1);
+    hipLaunchKernelGGL(k_batch_iterate<true>, grid, blk, 0, st, b.seqs, b.work, fin, b.s, b.health);
+    const int par = fin ^ 1;
+    hipLaunchKernelGGL(k_batch_stats, grid, blk, 0, st, b.seqs, b.work, par, b.partial);
+    hipLaunchKernelGGL(k_batch_final, dim3(b.n_seq), dim3(256), 0, st, b.seqs, b.partial, b.result);
+    return launch_batch_keyframe(b, par, st);
 }
 
 hipError_t launch_batch_passes(const BatchLaunch& b, int n_iters, bool prologue, bool final_last, hipStream_t st) {

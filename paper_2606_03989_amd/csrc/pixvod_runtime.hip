@@ -873,6 +873,7 @@ struct BatchSeq {
     float *Is = nullptr, *cxt = nullptr, *cyt = nullptr, *sig = nullptr;
     float *It = nullptr, *Gx = nullptr, *Gy = nullptr, *var_ll = nullptr, *valid = nullptr;
     float *frame = nullptr, *kf_stage = nullptr, *out_stage = nullptr, *dense = nullptr;
+    float* normals_stage = nullptr;      // staged normals of host-input frames (re-anchoring steps)
     bool have_kf = false, have_track = false;
     double T_w_kf[16];
     double xi_last[6];
@@ -892,9 +893,16 @@ struct pixvod_batch {
     double *d_partial = nullptr, *d_result = nullptr, *h_result = nullptr;
     int *d_health = nullptr, *h_health = nullptr;
     int parity = 0;
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
-    hipGraph_t graph[2] = {nullptr, nullptr};
+    // captured frame steps per (canonical buffer, re-anchoring on/off) for graph_iters iterations
+    hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    hipGraph_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     int graph_iters = -1;
+    std::vector<SeqDesc> descs;          // host copy of the device descriptors
+    SeqDesc* h_desc = nullptr;           // pinned staging of the descriptors
+    int *d_fsk = nullptr;                // per sequence: frames since the keyframe (device keyframe test)
+    unsigned *d_flags = nullptr, *h_flags = nullptr;
+    bool persistent = false;             // iteration block as one cooperative launch
+    int persistent_grid = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double last_ms = 0.0;
     std::string err;
@@ -934,12 +942,13 @@ static Strengths strengths_of_params(const pixvod_params& P) {
 }
 
 static void batch_drop_graphs(pixvod_batch* b) {
-    for (int k = 0; k < 2; ++k) {
-        if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
-        if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
-        b->exec[k] = nullptr;
-        b->graph[k] = nullptr;
-    }
+    for (int k = 0; k < 2; ++k)
+        for (int r = 0; r < 2; ++r) {
+            if (b->exec[k][r]) (void)hipGraphExecDestroy(b->exec[k][r]);
+            if (b->graph[k][r]) (void)hipGraphDestroy(b->graph[k][r]);
+            b->exec[k][r] = nullptr;
+            b->graph[k][r] = nullptr;
+        }
     b->graph_iters = -1;
 }
 
@@ -947,15 +956,17 @@ static void batch_release(pixvod_batch* b) {
     batch_drop_graphs(b);
     for (auto& q : b->seq) {
         void* bufs[] = {q.X[0], q.X[1], q.Is, q.cxt, q.cyt, q.sig, q.It, q.Gx, q.Gy, q.var_ll, q.valid,
-                        q.frame, q.kf_stage, q.out_stage, q.dense};
+                        q.frame, q.kf_stage, q.out_stage, q.dense, q.normals_stage};
         for (void* p : bufs)
             if (p) (void)hipFree(p);
     }
-    void* bufs[] = {b->d_seqs, b->d_work, b->d_partial, b->d_result, b->d_health};
+    void* bufs[] = {b->d_seqs, b->d_work, b->d_partial, b->d_result, b->d_health, b->d_fsk, b->d_flags};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     if (b->h_result) (void)hipHostFree(b->h_result);
     if (b->h_health) (void)hipHostFree(b->h_health);
+    if (b->h_flags) (void)hipHostFree(b->h_flags);
+    if (b->h_desc) (void)hipHostFree(b->h_desc);
     if (b->ev0) (void)hipEventDestroy(b->ev0);
     if (b->ev1) (void)hipEventDestroy(b->ev1);
     if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
@@ -984,9 +995,13 @@ static int batch_build_work(pixvod_batch* b) {
         d.var_ll = q.var_ll;
         d.valid = q.valid;
         d.frame = q.frame;
+        d.normals = nullptr;
         d.It = q.It;
         d.Gx = q.Gx;
         d.Gy = q.Gy;
+        d.Is = q.Is;
+        d.cxt = q.cxt;
+        d.cyt = q.cyt;
         d.tiles_x = (q.W + b->tile_x - 1) / b->tile_x;
         const int ty = (q.H + b->tile_y - 1) / b->tile_y;
         d.n_tiles = d.tiles_x * ty;
@@ -1010,7 +1025,9 @@ static int batch_build_work(pixvod_batch* b) {
         return bfail(b, PIXVOD_ENOMEM, "work list allocation failed");
     HIP_TRY_B(b, hipMemcpy(b->d_work, work.data(), sizeof(int2) * total, hipMemcpyHostToDevice));
     HIP_TRY_B(b, hipMemcpy(b->d_seqs, descs.data(), sizeof(SeqDesc) * b->n, hipMemcpyHostToDevice));
+    b->descs = descs;
     b->n_work = total;
+    b->persistent_grid = 0;
     batch_drop_graphs(b);
     return PIXVOD_OK;
 }
@@ -1028,6 +1045,11 @@ static BatchLaunch batch_launch_args(const pixvod_batch* b) {
     L.health = b->d_health;
     L.partial = b->d_partial;
     L.result = b->d_result;
+    L.fsk = b->d_fsk;
+    L.flags = b->d_flags;
+    L.kf_max_frames = b->P.kf_max_frames;
+    L.kf_min_valid = b->P.kf_min_valid_frac;
+    L.reanchor = 0;
     return L;
 }
 
@@ -1096,6 +1118,10 @@ int pixvod_batch_create(int n, const int* H, const int* W, const pixvod_intrinsi
     if (!rc && hipMalloc((void**)&b->d_health, sizeof(int)) != hipSuccess) rc = PIXVOD_ENOMEM;
     if (!rc && hipHostMalloc((void**)&b->h_result, sizeof(double) * 8 * n) != hipSuccess) rc = PIXVOD_ENOMEM;
     if (!rc && hipHostMalloc((void**)&b->h_health, sizeof(int)) != hipSuccess) rc = PIXVOD_ENOMEM;
+    if (!rc && hipMalloc((void**)&b->d_fsk, sizeof(int) * n) != hipSuccess) rc = PIXVOD_ENOMEM;
+    if (!rc && hipMalloc((void**)&b->d_flags, sizeof(unsigned) * n) != hipSuccess) rc = PIXVOD_ENOMEM;
+    if (!rc && hipHostMalloc((void**)&b->h_flags, sizeof(unsigned) * n) != hipSuccess) rc = PIXVOD_ENOMEM;
+    if (!rc && hipHostMalloc((void**)&b->h_desc, sizeof(SeqDesc) * n) != hipSuccess) rc = PIXVOD_ENOMEM;
     if (!rc && hipStreamCreateWithFlags(&b->own_stream, hipStreamNonBlocking) != hipSuccess) rc = PIXVOD_EHIP;
     if (!rc && (hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess)) rc = PIXVOD_EHIP;
     if (!rc) rc = batch_build_work(b);
@@ -1110,6 +1136,7 @@ int pixvod_batch_create(int n, const int* H, const int* W, const pixvod_intrinsi
                 break;
             }
         }
+        if (!rc && launch_set_ints(b->d_fsk, n, 0, b->own_stream) != hipSuccess) rc = PIXVOD_EHIP;
         if (!rc && hipStreamSynchronize(b->own_stream) != hipSuccess) rc = PIXVOD_EHIP;
     }
     if (rc) {
@@ -1171,6 +1198,7 @@ int pixvod_batch_set_keyframes(pixvod_batch* b, int m, const int* ids, const flo
         q.have_track = false;
         q.have_kf = true;
         q.frames_since_kf = 0;
+        HIP_TRY_B(b, launch_set_ints(b->d_fsk + ids[k], 1, 0, b->stream));
     }
     HIP_TRY_B(b, hipStreamSynchronize(b->stream));
     return PIXVOD_OK;
@@ -1186,11 +1214,12 @@ int pixvod_batch_set_tile(pixvod_batch* b, int tx, int ty) {
 }
 
 // graph of one frame step for the current parity
-static int batch_graph(pixvod_batch* b, int n_iters, hipGraphExec_t* exec) {
+static int batch_graph(pixvod_batch* b, int n_iters, int reanchor, hipGraphExec_t* exec) {
     if (b->graph_iters != n_iters) batch_drop_graphs(b);
     const int k = b->parity;
-    if (!b->exec[k]) {
-        const BatchLaunch L = batch_launch_args(b);
+    if (!b->exec[k][reanchor]) {
+        BatchLaunch L = batch_launch_args(b);
+        L.reanchor = reanchor;
         HIP_TRY_B(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
         hipError_t le = launch_batch_frame_step(L, n_iters, b->stream);
         hipGraph_t g = nullptr;
@@ -1200,42 +1229,73 @@ static int batch_graph(pixvod_batch* b, int n_iters, hipGraphExec_t* exec) {
             return bfail(b, PIXVOD_EHIP, std::string("graph capture failed: ") +
                                              hipGetErrorString(le != hipSuccess ? le : ce));
         }
-        b->graph[k] = g;
-        HIP_TRY_B(b, hipGraphInstantiate(&b->exec[k], g, nullptr, nullptr, 0));
+        b->graph[k][reanchor] = g;
+        HIP_TRY_B(b, hipGraphInstantiate(&b->exec[k][reanchor], g, nullptr, nullptr, 0));
         b->graph_iters = n_iters;
     }
-    *exec = b->exec[k];
+    *exec = b->exec[k][reanchor];
     return PIXVOD_OK;
 }
 
-int pixvod_batch_track(pixvod_batch* b, const float* const* frames, int where, int n_iters, pixvod_track_out* outs) {
-    if (!b) return bfail(nullptr, PIXVOD_EINVAL, "batch is NULL");
+// one frame step for every sequence; normals != NULL re-anchors, inside the
+// step, the sequences whose keyframe test fires on the frame just tracked
+static int batch_step(pixvod_batch* b, const float* const* frames, const float* const* normals, int where,
+                      int n_iters, pixvod_track_out* outs) {
     if (!frames || !outs) return bfail(b, PIXVOD_EINVAL, "frames and outs are required");
     if (where != PIXVOD_HOST && where != PIXVOD_DEVICE) return bfail(b, PIXVOD_EINVAL, "bad location");
     if (n_iters < 1) return bfail(b, PIXVOD_EINVAL, "n_iters must be >= 1");
+    const int reanchor = normals ? 1 : 0;
     for (int i = 0; i < b->n; ++i) {
-        if (!frames[i]) return bfail(b, PIXVOD_EINVAL, "missing frame");
+        if (!frames[i] || (reanchor && !normals[i])) return bfail(b, PIXVOD_EINVAL, "missing frame or normals");
         if (outs[i].out_where != PIXVOD_HOST && outs[i].out_where != PIXVOD_DEVICE)
             return bfail(b, PIXVOD_EINVAL, "bad output location");
         if (!b->seq[i].have_kf) return bfail(b, PIXVOD_ESTATE, "a sequence has no keyframe");
     }
+    // the step's frames (and normals): device inputs are read in place through
+    // the sequence descriptors, host inputs are staged first
     for (int i = 0; i < b->n; ++i) {
         BatchSeq& q = b->seq[i];
+        SeqDesc& d = b->descs[i];
         const size_t N = (size_t)q.H * q.W;
-        HIP_TRY_B(b, hipMemcpyAsync(q.frame, frames[i], N * sizeof(float),
-                                    where == PIXVOD_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
-                                    b->stream));
+        if (where == PIXVOD_HOST) {
+            HIP_TRY_B(b, hipMemcpyAsync(q.frame, frames[i], N * sizeof(float), hipMemcpyHostToDevice, b->stream));
+            d.frame = q.frame;
+            d.normals = nullptr;
+            if (reanchor) {
+                if (!q.normals_stage && hipMalloc((void**)&q.normals_stage, 3 * N * sizeof(float)) != hipSuccess)
+                    return bfail(b, PIXVOD_ENOMEM, "normal staging allocation failed");
+                HIP_TRY_B(b, hipMemcpyAsync(q.normals_stage, normals[i], 3 * N * sizeof(float),
+                                            hipMemcpyHostToDevice, b->stream));
+                d.normals = q.normals_stage;
+            }
+        } else {
+            d.frame = frames[i];
+            d.normals = reanchor ? normals[i] : nullptr;
+        }
     }
-    hipGraphExec_t exec = nullptr;
-    int rc = batch_graph(b, n_iters, &exec);
-    if (rc) return rc;
-    HIP_TRY_B(b, hipEventRecord(b->ev0, b->stream));
-    HIP_TRY_B(b, hipGraphLaunch(exec, b->stream));
-    HIP_TRY_B(b, hipEventRecord(b->ev1, b->stream));
+    std::memcpy(b->h_desc, b->descs.data(), sizeof(SeqDesc) * b->n);
+    HIP_TRY_B(b, hipMemcpyAsync(b->d_seqs, b->h_desc, sizeof(SeqDesc) * b->n, hipMemcpyHostToDevice, b->stream));
+    if (b->persistent) {
+        BatchLaunch L = batch_launch_args(b);
+        L.reanchor = reanchor;
+        if (!b->persistent_grid) b->persistent_grid = batch_persistent_grid(L);
+        if (b->persistent_grid < 1) return bfail(b, PIXVOD_EHIP, "no co-resident grid for the persistent step");
+        HIP_TRY_B(b, hipEventRecord(b->ev0, b->stream));
+        HIP_TRY_B(b, launch_batch_frame_step_persistent(L, n_iters, b->persistent_grid, b->stream));
+        HIP_TRY_B(b, hipEventRecord(b->ev1, b->stream));
+    } else {
+        hipGraphExec_t exec = nullptr;
+        int rc = batch_graph(b, n_iters, reanchor, &exec);
+        if (rc) return rc;
+        HIP_TRY_B(b, hipEventRecord(b->ev0, b->stream));
+        HIP_TRY_B(b, hipGraphLaunch(exec, b->stream));
+        HIP_TRY_B(b, hipEventRecord(b->ev1, b->stream));
+    }
     b->parity ^= (n_iters + 1) & 1;
     HIP_TRY_B(b, hipMemcpyAsync(b->h_result, b->d_result, sizeof(double) * 8 * b->n, hipMemcpyDeviceToHost,
                                 b->stream));
     HIP_TRY_B(b, hipMemcpyAsync(b->h_health, b->d_health, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY_B(b, hipMemcpyAsync(b->h_flags, b->d_flags, sizeof(unsigned) * b->n, hipMemcpyDeviceToHost, b->stream));
     for (int i = 0; i < b->n; ++i) {
         BatchSeq& q = b->seq[i];
         pixvod_track_out* o = &outs[i];
@@ -1247,6 +1307,8 @@ int pixvod_batch_track(pixvod_batch* b, const float* const* frames, int where, i
             di = o->inv_depth ? q.out_stage : nullptr;
             dv = o->inv_depth_var ? q.out_stage + N : nullptr;
         }
+        // re-anchoring keeps the log-depths and the variance plane: the maps
+        // are those of the frame just tracked
         HIP_TRY_B(b, launch_outputs(geo_of_seq(q), q.X[b->parity], q.var_ll, 1, di, dv, b->stream));
         if (o->out_where == PIXVOD_HOST) {
             if (o->inv_depth)
@@ -1274,15 +1336,36 @@ int pixvod_batch_track(pixvod_batch* b, const float* const* frames, int where, i
         host_se3_exp(q.xi_last, E);
         host_se3_inverse(E, Ei);
         host_mat4_mul(q.T_w_kf, Ei, o->T_world);
-        const float vf = (float)(b->h_result[8 * i + 6] * inv_n);
-        o->valid_fraction = vf;
+        o->valid_fraction = (float)(b->h_result[8 * i + 6] * inv_n);
         o->frames_since_keyframe = q.frames_since_kf;
-        unsigned f = 0;
-        if (q.frames_since_kf >= b->P.kf_max_frames || vf < b->P.kf_min_valid_frac) f |= PIXVOD_KEYFRAME_DUE;
-        if (vf < b->P.kf_min_valid_frac) f |= PIXVOD_LOW_OVERLAP;
-        if (b->h_result[8 * i + 7] > 0.0 || *b->h_health != 0) f |= PIXVOD_DIVERGED;
-        o->flags = f;
+        o->flags = b->h_flags[i];
+        if (reanchor && (o->flags & PIXVOD_KEYFRAME_DUE)) {
+            // re-anchored inside the step on the frame just tracked
+            std::memcpy(q.T_w_kf, o->T_world, sizeof(q.T_w_kf));
+            std::memset(q.xi_last, 0, sizeof(q.xi_last));
+            q.have_track = false;
+            q.frames_since_kf = 0;
+        }
     }
+    return PIXVOD_OK;
+}
+
+int pixvod_batch_track(pixvod_batch* b, const float* const* frames, int where, int n_iters, pixvod_track_out* outs) {
+    if (!b) return bfail(nullptr, PIXVOD_EINVAL, "batch is NULL");
+    return batch_step(b, frames, nullptr, where, n_iters, outs);
+}
+
+int pixvod_batch_track_reanchor(pixvod_batch* b, const float* const* frames, const float* const* normals,
+                                int where, int n_iters, pixvod_track_out* outs) {
+    if (!b) return bfail(nullptr, PIXVOD_EINVAL, "batch is NULL");
+    if (!normals) return bfail(b, PIXVOD_EINVAL, "normals are required");
+    return batch_step(b, frames, normals, where, n_iters, outs);
+}
+
+int pixvod_batch_set_persistent(pixvod_batch* b, int enable) {
+    if (!b) return bfail(nullptr, PIXVOD_EINVAL, "batch is NULL");
+    b->persistent = enable != 0;
+    b->persistent_grid = 0;
     return PIXVOD_OK;
 }
 

@@ -189,3 +189,56 @@ def test_full_size_mixed_batch_sampled_against_per_sequence():
         t.close()
     print(f"64-sequence batch frame step {b.last_step_ms():.2f} ms", flush=True)
     b.close()
+
+
+def test_device_reanchoring_equals_host_reanchoring():
+    # keyframe test and re-anchoring inside the captured frame step (device
+    # flag, predicated kernel) against per-sequence contexts re-anchored from
+    # the host when their flag fires; every second frame is due
+    import paper_2606_03989_amd as pv
+    seqs = _seq_inputs(SHAPES, 5)
+    params = dict(PARAMS, kf_max_frames=2)
+    b = pv.Batch([(s["cam"].H, s["cam"].W) for s in seqs], [_K(s["cam"]) for s in seqs], **params)
+    b.set_keyframes(list(range(len(seqs))), [s["I_s"] for s in seqs], [s["N_s"] for s in seqs])
+    singles = []
+    for s in seqs:
+        t = pv.Tracker(s["cam"].H, s["cam"].W, _K(s["cam"]), **params)
+        t.set_keyframe(s["I_s"], s["N_s"])
+        singles.append(t)
+    n_due = 0
+    for f in range(5):
+        rb = b.track([s["frames"][f] for s in seqs], 4, maps=True, normals=[s["N_s"] for s in seqs])
+        for i, (s, t) in enumerate(zip(seqs, singles)):
+            rs = t.track(s["frames"][f], 4)
+            assert rb[i]["flags"] == rs["flags"] and rb[i]["frames_since_keyframe"] == rs["frames_since_keyframe"]
+            np.testing.assert_array_equal(rb[i]["inv_depth"], rs["inv_depth"])
+            np.testing.assert_allclose(rb[i]["T_world"], rs["T_world"], rtol=1e-12, atol=1e-15)
+            if rs["flags"] & pv.KEYFRAME_DUE:
+                n_due += 1
+                t.set_keyframe(s["frames"][f], s["N_s"])
+            np.testing.assert_array_equal(b.get_state(i), t.get_state())
+    assert n_due >= 2 * len(seqs)
+    print(f"device re-anchoring: {n_due} re-anchorings over 5 frames, batch == host-side re-anchoring", flush=True)
+
+
+@pytest.mark.parametrize("reanchor", [False, True])
+def test_persistent_iteration_block_equals_launch_per_pass(reanchor):
+    import paper_2606_03989_amd as pv
+    seqs = _seq_inputs(SHAPES, 3)
+    params = dict(PARAMS, kf_max_frames=2)
+    batches = []
+    for persistent in (False, True):
+        b = pv.Batch([(s["cam"].H, s["cam"].W) for s in seqs], [_K(s["cam"]) for s in seqs], **params)
+        b.set_persistent(persistent)
+        b.set_keyframes(list(range(len(seqs))), [s["I_s"] for s in seqs], [s["N_s"] for s in seqs])
+        batches.append(b)
+    for f in range(3):
+        kw = dict(normals=[s["N_s"] for s in seqs]) if reanchor else {}
+        ra = batches[0].track([s["frames"][f] for s in seqs], 5, **kw)
+        rp = batches[1].track([s["frames"][f] for s in seqs], 5, **kw)
+        for i in range(len(seqs)):
+            np.testing.assert_array_equal(ra[i]["xi"], rp[i]["xi"])
+            assert ra[i]["flags"] == rp[i]["flags"]
+            np.testing.assert_array_equal(batches[0].get_state(i), batches[1].get_state(i))
+    print(f"persistent iteration block == one launch per pass (re-anchoring {reanchor}); "
+          f"step {batches[1].last_step_ms():.3f} ms against {batches[0].last_step_ms():.3f} ms", flush=True)

@@ -138,6 +138,31 @@ def run_gpu(args):
                     kernel="k_fu_iterate<false>", bytes_per_px_iter=BYTES_PER_PX_ITER,
                     avg_launch_us=round(avg_launch_s * 1e6, 2), launches=it_n)
 
+    # the frame step replayed as one graph against the same passes launched one
+    # by one, both without profiling events, on the same frames
+    def timed_steps(graph):
+        tt = make(pv.SCHED_FUSED)
+        tt.set_graph(graph)
+        for i in range(args.warmup):
+            step(tt, i, iters)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for i in range(args.warmup, args.warmup + args.steps):
+            step(tt, i, iters)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - a
+        tt.close()
+        return dt * 1e3 / args.steps
+
+    g_ms, u_ms = timed_steps(True), timed_steps(False)
+    passes_ms = (it_ms + fin_ms + pro_ms) / args.steps
+    frame_step = dict(graph_ms=round(g_ms, 3), unrolled_ms=round(u_ms, 3), passes_ms=round(passes_ms, 3),
+                      overhead_graph_us=round((g_ms - passes_ms) * 1e3, 1),
+                      overhead_unrolled_us=round((u_ms - passes_ms) * 1e3, 1),
+                      overhead_removed_us=round((u_ms - g_ms) * 1e3, 1))
+    log(f"frame step: graph replay {g_ms:.3f} ms, passes launched one by one {u_ms:.3f} ms, "
+        f"prologue + passes {passes_ms:.3f} ms: {(u_ms - g_ms) * 1e3:.1f} us per frame removed by the graph")
+
     # the per-factor schedule on the same frames (row a13 baseline)
     per_factor = None
     if args.per_factor_steps > 0:
@@ -163,7 +188,8 @@ def run_gpu(args):
         log(f"per-factor: {pf_value:.1f} Mpx-iter/s, iteration {pf_launch * 1e6:.1f} us")
         tp.close()
     t.close()
-    return dict(value=value, elapsed=elapsed, roofline=roofline, per_factor=per_factor, H=H, W=W, iters=iters,
+    return dict(value=value, elapsed=elapsed, roofline=roofline, per_factor=per_factor, frame_step=frame_step,
+                H=H, W=W, iters=iters,
                 pass_us=avg_launch_s * 1e6, inputs=(cam, d_I0, d_N0, d_frames, d_normals, stream))
 
 
@@ -916,6 +942,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "storage_dtype": "f32",
+        "precision": "fp32 storage, fp64 arithmetic",
         "data": "synthetic",
         "config": {"workload": "vga640x480 piecewise-planar sequence, 20 GBP iterations per frame, fused schedule",
                    "H": g["H"], "W": g["W"], "iters_per_frame": g["iters"], "state": "fp32 SoA, 123 planes",
@@ -923,6 +950,7 @@ def main():
         "roofline": g["roofline"],
         "cpu_baseline": cpu,
         "per_factor": g["per_factor"],
+        "frame_step": g["frame_step"],
         "batched": batched,
         "forward_adjoint": adjoint,
         "quadtree": quadtree,

@@ -195,6 +195,11 @@ int pixvod_set_sigma_map(pixvod_ctx* ctx, const float* sigma_D_map, int where);
  * warm-started from the previous frame's state (Sec. 4.3), then the pose
  * estimate, output maps, keyframe test and flags. Returns after the pose is
  * on the host; device output maps are written in stream order.
+ * With pixvod_set_graph enabled, the fused schedule on the grid topology
+ * captures the frame step (prologue, n_iters passes, frame reductions) once
+ * as a HIP graph per starting state buffer and replays it; it is captured
+ * again whenever a kernel argument changes (parameters, bound maps, n_iters,
+ * profiling). Results are identical to launching the passes one by one.
  * PIXVOD_ESTATE before the first pixvod_set_keyframe. */
 int pixvod_track(pixvod_ctx* ctx, const float* frame, int where, int n_iters,
                  pixvod_track_out* out);
@@ -234,9 +239,12 @@ int pixvod_get_state(pixvod_ctx* ctx, void* dst, int where);
 int pixvod_set_state(pixvod_ctx* ctx, const void* src, int where);
 
 /* Kernel timing for benchmarks. With profiling enabled, the context records
- * a HIP event pair on its stream around every launch of the passes below;
- * pixvod_profile_read() waits for the stream, returns the summed duration in
- * milliseconds and the launch count of one pass kind, and resets that kind. */
+ * a HIP event pair on its stream around each run of consecutive launches of
+ * one pass kind below (per frame: the prologue, the n_iters - 1 fused passes,
+ * the last pass; all per-factor iterations); pixvod_profile_read() waits for
+ * the stream, returns the summed duration in milliseconds and the launch
+ * count of one pass kind, and resets that kind. Durations of a run include
+ * the gaps between its launches. */
 enum {
     PIXVOD_PROF_FUSED_ITERATE = 0,    /* one fused iteration pass (not the last of a frame) */
     PIXVOD_PROF_FUSED_FINAL = 1,      /* the last fused pass of a frame */
@@ -245,6 +253,13 @@ enum {
     PIXVOD_PROF_KINDS = 4
 };
 int pixvod_profile_enable(pixvod_ctx* ctx, int enable);
+/* With profiling enabled, replayed frame steps time their passes with event
+ * nodes captured in the graph; where the runtime cannot capture them the
+ * frame steps of a profiled context launch their passes one by one. */
+
+/* enable != 0: pixvod_track replays the captured frame step; 0 (default):
+ * every pass is launched on its own. */
+int pixvod_set_graph(pixvod_ctx* ctx, int enable);
 int pixvod_profile_read(pixvod_ctx* ctx, int kind, double* total_ms, int64_t* launches);
 
 /* ---------------------------------------------------------------------------

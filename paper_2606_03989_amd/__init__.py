@@ -87,6 +87,7 @@ _SIGNATURES = {
     "pixvod_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "pixvod_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "pixvod_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
+    "pixvod_set_graph": (C.c_int, [C.c_void_p, C.c_int]),
     "pixvod_profile_read": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "pixvod_batch_create": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(Intrinsics),
                                       C.POINTER(Params), C.POINTER(C.c_void_p)]),
@@ -308,6 +309,10 @@ class Tracker(_FollowsTorchStream):
 
     def profile(self, enable: bool = True):
         _check(lib().pixvod_profile_enable(self._h, 1 if enable else 0), self._h)
+
+    def set_graph(self, enable: bool = True):
+        """Replay the captured frame step, or launch every pass on its own (default)."""
+        _check(lib().pixvod_set_graph(self._h, 1 if enable else 0), self._h)
 
     def profile_read(self, kind: int):
         """(total milliseconds, launches) of one timed pass kind; resets it."""

@@ -319,67 +319,80 @@ __device__ inline void unary_adjoint(const Geo& g, const Strengths& s, const Inp
         se3_compose(s.prior_R, s.prior_t, R, t, Rr, tr);
         se3_log(Rr, tr, rp);
     }
-    double ad[36];
+    // J = [[S, 0], [Q, S]] as in unary_factors: S = I + W/2 + W^2/12,
+    // Q = P/2 + (PW + WP)/12 with W = [w]x, P = [q]x, rp = (w, q)
+    const double w0 = rp[0], w1 = rp[1], w2 = rp[2], p0 = rp[3], p1 = rp[4], p2 = rp[5];
+    const double Wm[9] = {0.0, -w2, w1, w2, 0.0, -w0, -w1, w0, 0.0};
+    const double Pm[9] = {0.0, -p2, p1, p2, 0.0, -p0, -p1, p0, 0.0};
+    double S[9], Q[9];
     {
-        const double w0 = rp[0], w1 = rp[1], w2 = rp[2], p0 = rp[3], p1 = rp[4], p2 = rp[5];
-        const double Wm[9] = {0.0, -w2, w1, w2, 0.0, -w0, -w1, w0, 0.0};
-        const double Pm[9] = {0.0, -p2, p1, p2, 0.0, -p0, -p1, p0, 0.0};
+        const double w[3] = {w0, w1, w2}, q[3] = {p0, p1, p2};
+        const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
+        const double wq = w0 * p0 + w1 * p1 + w2 * p2;
+        constexpr double c12 = 1.0 / 12.0;
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                ad[r * 6 + c] = Wm[r * 3 + c];
-                ad[r * 6 + c + 3] = 0.0;
-                ad[(r + 3) * 6 + c] = Pm[r * 3 + c];
-                ad[(r + 3) * 6 + c + 3] = Wm[r * 3 + c];
+                const double I = (r == c) ? 1.0 : 0.0;
+                S[r * 3 + c] = I + 0.5 * Wm[r * 3 + c] + (w[r] * w[c] - I * th2) * c12;
+                Q[r * 3 + c] = 0.5 * Pm[r * 3 + c] + (w[r] * q[c] + q[r] * w[c] - 2.0 * I * wq) * c12;
             }
     }
-    double Jp[36];
-#pragma unroll
-    for (int r = 0; r < 6; ++r)
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            double a2s = 0.0;
-#pragma unroll
-            for (int k = 0; k < 6; ++k) a2s += ad[r * 6 + k] * ad[k * 6 + c];
-            Jp[r * 6 + c] = (r == c ? 1.0 : 0.0) + 0.5 * ad[r * 6 + c] + a2s * (1.0 / 12.0);
-        }
     const double lamP = s.lamP;
-    // Jp_bar = lamP (2 Jp S - rp eb_p^T), S the half-weight matrix of Lb's pose block
-    double Jpb[36], rpb[6];
+    // eta_p -= lamP J^T rp: rp_bar = -lamP J eb_p
+    double rpb[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        double e = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double e0 = 0.0, e1 = 0.0;
 #pragma unroll
-        for (int a = 0; a < 6; ++a) e += Jp[k * 6 + a] * eb[a];
-        rpb[k] = -lamP * e;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            double js = 0.0;
-#pragma unroll
-            for (int bb = 0; bb < 6; ++bb) js += Jp[k * 6 + bb] * (bb == c ? 2.0 : 1.0) * Lb[s7(bb, c)];
-            Jpb[k * 6 + c] = lamP * (js - rp[k] * eb[c]);
+        for (int a = 0; a < 3; ++a) {
+            e0 += S[k * 3 + a] * eb[a];
+            e1 += Q[k * 3 + a] * eb[a] + S[k * 3 + a] * eb[3 + a];
         }
+        rpb[k] = -lamP * e0;
+        rpb[3 + k] = -lamP * e1;
     }
-    // through Jp(rp): ad_bar = Jp_bar / 2 + (Jp_bar ad^T + ad^T Jp_bar) / 12
-    double Adb[36];
+    // L_pp += lamP J^T J: J_bar = lamP (J M - rp eb_p^T), M the pose block of
+    // Lb with a doubled diagonal; S enters both diagonal blocks, Q the lower
+    // left one (the upper right block of J is identically zero)
+    double Sb[9], Qb[9];
 #pragma unroll
-    for (int r = 0; r < 6; ++r)
+    for (int k = 0; k < 3; ++k)
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            double x = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            double tl = 0.0, bl = 0.0, br = 0.0;
 #pragma unroll
-            for (int k = 0; k < 6; ++k) x += Jpb[r * 6 + k] * ad[c * 6 + k] + ad[k * 6 + r] * Jpb[k * 6 + c];
-            Adb[r * 6 + c] = 0.5 * Jpb[r * 6 + c] + x * (1.0 / 12.0);
+            for (int j = 0; j < 3; ++j) {
+                const double m_jc = (j == c ? 2.0 : 1.0) * Lb[s7(j, c)];
+                const double m_j3c = Lb[s7(j, 3 + c)];
+                const double m_3jc = Lb[s7(3 + j, c)];
+                const double m_3j3c = (j == c ? 2.0 : 1.0) * Lb[s7(3 + j, 3 + c)];
+                tl += S[k * 3 + j] * m_jc;
+                bl += Q[k * 3 + j] * m_jc + S[k * 3 + j] * m_3jc;
+                br += Q[k * 3 + j] * m_j3c + S[k * 3 + j] * m_3j3c;
+            }
+            Sb[k * 3 + c] = lamP * ((tl - rp[k] * eb[c]) + (br - rp[3 + k] * eb[3 + c]));
+            Qb[k * 3 + c] = lamP * (bl - rp[3 + k] * eb[c]);
         }
+    // through S(w) and Q(w, q), with W^T = -W and P^T = -P:
+    //   W_bar = Sb/2 - (Sb W + W Sb)/12 - (P Qb + Qb P)/12,
+    //   P_bar = Qb/2 - (Qb W + W Qb)/12
     {
         double Wb[9], Pb[9];
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                Wb[r * 3 + c] = Adb[r * 6 + c] + Adb[(r + 3) * 6 + c + 3];
-                Pb[r * 3 + c] = Adb[(r + 3) * 6 + c];
+                double sw = 0.0, pq = 0.0, qw = 0.0;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    sw += Sb[r * 3 + j] * Wm[j * 3 + c] + Wm[r * 3 + j] * Sb[j * 3 + c];
+                    pq += Pm[r * 3 + j] * Qb[j * 3 + c] + Qb[r * 3 + j] * Pm[j * 3 + c];
+                    qw += Qb[r * 3 + j] * Wm[j * 3 + c] + Wm[r * 3 + j] * Qb[j * 3 + c];
+                }
+                Wb[r * 3 + c] = 0.5 * Sb[r * 3 + c] - (sw + pq) * (1.0 / 12.0);
+                Pb[r * 3 + c] = 0.5 * Qb[r * 3 + c] - qw * (1.0 / 12.0);
             }
         rpb[0] += Wb[7] - Wb[5];
         rpb[1] += Wb[2] - Wb[6];
@@ -389,15 +402,27 @@ __device__ inline void unary_adjoint(const Geo& g, const Strengths& s, const Inp
         rpb[5] += Pb[3] - Pb[1];
     }
     ell_bar += -lamP * eb[6];
+    // both targets are updated unconditionally (one of the two increments is
+    // zero): stores into tau_bar or eps_bar chosen by a branch would be merged
+    // into stores through a selected pointer, which keeps both arrays in
+    // scratch memory
+    double dtau[6], deps[6];
     if (s.prior_is_identity) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) tau_bar[k] += rpb[k];
+        for (int k = 0; k < 6; ++k) {
+            dtau[k] = rpb[k];
+            deps[k] = 0.0;
+        }
     } else {
         // rp = Log(Exp(prior)^-1 Exp(tau)): d rp = Jr(rp)^-1 eps
-        double e6[6];
-        jac_invT_apply(rp, -1.0, rpb, e6);
+        jac_invT_apply(rp, -1.0, rpb, deps);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) eps_bar[k] += e6[k];
+        for (int k = 0; k < 6; ++k) dtau[k] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        tau_bar[k] += dtau[k];
+        eps_bar[k] += deps[k];
     }
 }
 
@@ -473,13 +498,14 @@ __device__ inline void marginals_adjoint(const double L[28], const double eta[7]
 __device__ inline void identity_partial_adjoint(double lamR, const double V[21], const double v[6],
                                                 const double Lpb[21], const double hb[6], double Vb[21],
                                                 double vb[6]) {
-    double A[21], idg[6], Ai[21];
+    double A[21], Ai[21];
 #pragma unroll
     for (int k = 0; k < 21; ++k) A[k] = V[k];
 #pragma unroll
     for (int k = 0; k < 6; ++k) A[s6(k, k)] += lamR;
-    chol6(A, idg);
-    chol6_inverse(A, idg, Ai);
+    sweep6_neg_inverse(A);
+#pragma unroll
+    for (int k = 0; k < 21; ++k) Ai[k] = -A[k];
     // cotangent of the packed inverse
     double Aib[21];
     const double l2 = lamR * lamR;

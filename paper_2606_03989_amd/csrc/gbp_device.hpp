@@ -211,7 +211,9 @@ __device__ inline void so3_log(const double R[9], double w[3], double& th2) {
         w[2] = f * v2;
         return;
     }
-    // near pi: axis from the diagonal (not reached by tracking motions)
+    // near pi: axis from the diagonal (not reached by tracking motions); the
+    // largest diagonal entry k picks the column, by selects rather than a
+    // computed index so that R stays in registers
     double n[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -219,9 +221,17 @@ __device__ inline void so3_log(const double R[9], double w[3], double& th2) {
         n[i] = sqrt(d > 0.0 ? d : 0.0);
     }
     const int k = (n[0] >= n[1] && n[0] >= n[2]) ? 0 : (n[1] >= n[2] ? 1 : 2);
+    const double nk = (k == 0) ? n[0] : (k == 1 ? n[1] : n[2]);
+    double m[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
-        if (i != k) n[i] = (R[i * 3 + k] + R[k * 3 + i]) / (4.0 * n[k]);
+    for (int i = 0; i < 3; ++i) {
+        // (R[i][k] + R[k][i]) / (4 n_k) for i != k
+        const double rik = (k == 0) ? R[i * 3] : (k == 1 ? R[i * 3 + 1] : R[i * 3 + 2]);
+        const double rki = (k == 0) ? R[i] : (k == 1 ? R[3 + i] : R[6 + i]);
+        m[i] = (i == k) ? n[i] : (rik + rki) / (4.0 * nk);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) n[i] = m[i];
     double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
     if (n[0] * v0 + n[1] * v1 + n[2] * v2 < 0.0) nn = -nn;
     w[0] = th * n[0] / nn;
@@ -507,49 +517,58 @@ __device__ inline bool unary_factors(const Geo& g, const Strengths& s, const Inp
         se3_compose(s.prior_R, s.prior_t, R, t, Rr, tr);
         se3_log(Rr, tr, rp);
     }
-    // ad = [[W, 0], [P, W]] with W = [theta]x, P = [rho]x
-    double Jp[36];
+    // J = [[S, 0], [Q, S]] with, for rp = (w, q), W = [w]x, P = [q]x and
+    // [a]x [b]x = b a^T - (a.b) I:
+    //   S = I + W/2 + W^2/12 = I + W/2 + (w w^T - |w|^2 I)/12,
+    //   Q = P/2 + (PW + WP)/12 = P/2 + (w q^T + q w^T - 2 (w.q) I)/12
+    double S[9], Q[9];
     {
         const double w0 = rp[0], w1 = rp[1], w2 = rp[2], p0 = rp[3], p1 = rp[4], p2 = rp[5];
+        const double w[3] = {w0, w1, w2}, q[3] = {p0, p1, p2};
         const double Wm[9] = {0.0, -w2, w1, w2, 0.0, -w0, -w1, w0, 0.0};
         const double Pm[9] = {0.0, -p2, p1, p2, 0.0, -p0, -p1, p0, 0.0};
-        double WW[9], PW[9], WP[9];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                WW[r * 3 + c] = Wm[r * 3] * Wm[c] + Wm[r * 3 + 1] * Wm[3 + c] + Wm[r * 3 + 2] * Wm[6 + c];
-                PW[r * 3 + c] = Pm[r * 3] * Wm[c] + Pm[r * 3 + 1] * Wm[3 + c] + Pm[r * 3 + 2] * Wm[6 + c];
-                WP[r * 3 + c] = Wm[r * 3] * Pm[c] + Wm[r * 3 + 1] * Pm[3 + c] + Wm[r * 3 + 2] * Pm[6 + c];
-            }
-        // ad^2 = [[W^2, 0], [PW + WP, W^2]]
+        const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
+        const double wq = w0 * p0 + w1 * p1 + w2 * p2;
+        constexpr double c12 = 1.0 / 12.0;
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const double I = (r == c) ? 1.0 : 0.0;
-                const double top = I + 0.5 * Wm[r * 3 + c] + WW[r * 3 + c] * (1.0 / 12.0);
-                Jp[r * 6 + c] = top;
-                Jp[r * 6 + c + 3] = 0.0;
-                Jp[(r + 3) * 6 + c] = 0.5 * Pm[r * 3 + c] + (PW[r * 3 + c] + WP[r * 3 + c]) * (1.0 / 12.0);
-                Jp[(r + 3) * 6 + c + 3] = top;
+                S[r * 3 + c] = I + 0.5 * Wm[r * 3 + c] + (w[r] * w[c] - I * th2) * c12;
+                Q[r * 3 + c] = 0.5 * Pm[r * 3 + c] + (w[r] * q[c] + q[r] * w[c] - 2.0 * I * wq) * c12;
             }
     }
-    // J^T J and J^T r with J = [[S, 0], [Q, S]] (S top-left block, Q bottom-left)
+    // J^T J = [[S^T S + Q^T Q, Q^T S], [S^T Q, S^T S]],
+    // J^T rp = [S^T rp_w + Q^T rp_q; S^T rp_q]
     const double lamP = s.lamP;
 #pragma unroll
-    for (int a = 0; a < 6; ++a) {
-        double e = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double e0 = 0.0, e1 = 0.0;
 #pragma unroll
-        for (int k = (a < 3 ? 0 : 3); k < 6; ++k) e += Jp[k * 6 + a] * rp[k];
-        eta[a] -= lamP * e;
+        for (int k = 0; k < 3; ++k) {
+            e0 += S[k * 3 + a] * rp[k] + Q[k * 3 + a] * rp[3 + k];
+            e1 += S[k * 3 + a] * rp[3 + k];
+        }
+        eta[a] -= lamP * e0;
+        eta[3 + a] -= lamP * e1;
 #pragma unroll
-        for (int b = a; b < 6; ++b) {
-            double g = 0.0;
-            const int k0 = (a < 3 && b < 3) ? 0 : 3;
+        for (int b = a; b < 3; ++b) {
+            double ss = 0.0, qq = 0.0;
 #pragma unroll
-            for (int k = k0; k < 6; ++k) g += Jp[k * 6 + a] * Jp[k * 6 + b];
-            L[s7(a, b)] += lamP * g;
+            for (int k = 0; k < 3; ++k) {
+                ss += S[k * 3 + a] * S[k * 3 + b];
+                qq += Q[k * 3 + a] * Q[k * 3 + b];
+            }
+            L[s7(a, b)] += lamP * (ss + qq);
+            L[s7(3 + a, 3 + b)] += lamP * ss;
+        }
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            double qs = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) qs += Q[k * 3 + a] * S[k * 3 + b];
+            L[s7(a, 3 + b)] += lamP * qs;
         }
     }
     const double pell = s.has_prior_map ? (double)pin.prior_ell : s.prior_ell;
@@ -680,23 +699,46 @@ __device__ inline void add_messages(double L[28], double eta[7], const float mid
 // Identity factor (Eq. regul) with Jacobians +I / -I: for the sender's
 // variable-to-factor pose marginal (V, v) and A = lamR I + V,
 //   Lambda' = lamR I - lamR^2 A^-1,   h = lamR A^-1 v,   eta' = h - Lambda' r.
+// A^-1 comes from symmetric Gauss-Jordan elimination (the sweep operator on
+// each pivot in turn), which leaves -A^-1 in the packed storage; every pivot
+// is a Schur complement of A, so a non-positive one means A is not SPD.
+__device__ inline bool sweep6_neg_inverse(double A[21]) {
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double D = A[s6(k, k)];
+        ok = ok && (D > 0.0);
+        const double iD = rcp_nr(D > 0.0 ? D : 1e-300);
+        double r[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) r[i] = (i == k) ? 0.0 : A[s6(i, k)] * iD;
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+#pragma unroll
+            for (int j = i; j < 6; ++j)
+                if (i != k && j != k) A[s6(i, j)] = fma(-A[s6(i, k)], r[j], A[s6(i, j)]);
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+            if (i != k) A[s6(i, k)] = r[i];
+        A[s6(k, k)] = -iD;
+    }
+    return ok;
+}
+
 __device__ inline bool identity_partial(double lamR, double V[21], const double v[6], double Lp[21],
                                         double h[6]) {
-    double idg[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) V[s6(k, k)] += lamR;
-    const bool ok = chol6(V, idg);
-    double Ai[21];
-    chol6_inverse(V, idg, Ai);
+    const bool ok = sweep6_neg_inverse(V);          // V <- -A^-1
     const double l2 = lamR * lamR;
 #pragma unroll
     for (int r = 0; r < 6; ++r) {
         double s = 0.0;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) s += Ai[s6(r, c)] * v[c];
-        h[r] = lamR * s;
+        for (int c = 0; c < 6; ++c) s = fma(V[s6(r, c)], v[c], s);
+        h[r] = -lamR * s;
 #pragma unroll
-        for (int c = r; c < 6; ++c) Lp[s6(r, c)] = (r == c ? lamR : 0.0) - l2 * Ai[s6(r, c)];
+        for (int c = r; c < 6; ++c) Lp[s6(r, c)] = fma(l2, V[s6(r, c)], r == c ? lamR : 0.0);
     }
     return ok;
 }

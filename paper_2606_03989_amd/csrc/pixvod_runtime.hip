@@ -60,10 +60,22 @@ struct pixvod_ctx {
     // kernel timing
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
-    struct Pending { hipEvent_t a, b; int kind; };
+    struct Pending { hipEvent_t a, b; int kind; int launches; };
     std::vector<Pending> pending;
     double prof_ms[PIXVOD_PROF_KINDS] = {0, 0, 0, 0};
     int64_t prof_n[PIXVOD_PROF_KINDS] = {0, 0, 0, 0};
+    // captured frame steps of the fused grid schedule, one per starting
+    // buffer; `key` holds the bytes of every captured kernel argument
+    struct TrackGraph {
+        hipGraphExec_t exec = nullptr;
+        std::vector<unsigned char> key;
+        std::vector<hipEvent_t> ev;      // profiled graphs: an event pair per timed run of launches
+        std::vector<int> kind, launches;
+    };
+    bool use_graph = false;
+    std::vector<Pending> graph_pending;  // event pairs owned by a graph, read after its replay
+    bool graph_events_ok = true;         // event nodes can be captured for profiling
+    TrackGraph tgraph[2];
 };
 
 // ---------------------------------------------------------------------------
@@ -252,7 +264,8 @@ static hipEvent_t prof_begin(pixvod_ctx* c) {
     return a;
 }
 
-static void prof_end(pixvod_ctx* c, hipEvent_t a, int kind) {
+// closes a timed run of `launches` consecutive launches of one kind
+static void prof_end(pixvod_ctx* c, hipEvent_t a, int kind, int launches = 1) {
     if (!a) return;
     hipEvent_t b = take_event(c);
     if (!b) {
@@ -260,7 +273,7 @@ static void prof_end(pixvod_ctx* c, hipEvent_t a, int kind) {
         return;
     }
     (void)hipEventRecord(b, c->stream);
-    c->pending.push_back({a, b, kind});
+    c->pending.push_back({a, b, kind, launches});
 }
 
 // folds completed event pairs into the per-kind totals (stream must be idle)
@@ -269,12 +282,20 @@ static void prof_collect(pixvod_ctx* c) {
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
             c->prof_ms[p.kind] += ms;
-            c->prof_n[p.kind] += 1;
+            c->prof_n[p.kind] += p.launches;
         }
         c->ev_pool.push_back(p.a);
         c->ev_pool.push_back(p.b);
     }
     c->pending.clear();
+    for (auto& p : c->graph_pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            c->prof_ms[p.kind] += ms;
+            c->prof_n[p.kind] += p.launches;
+        }
+    }
+    c->graph_pending.clear();
 }
 
 static void release(pixvod_ctx* c) {
@@ -285,6 +306,10 @@ static void release(pixvod_ctx* c) {
         if (b) (void)hipFree(b);
     if (c->h_result) (void)hipHostFree(c->h_result);
     if (c->h_health) (void)hipHostFree(c->h_health);
+    for (auto& t : c->tgraph) {
+        if (t.exec) (void)hipGraphExecDestroy(t.exec);
+        for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
+    }
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     for (auto& p : c->pending) {
         c->ev_pool.push_back(p.a);
@@ -638,15 +663,20 @@ static int run_iterations(pixvod_ctx* c, int n) {
                                         c->stream));
         prof_end(c, a, PIXVOD_PROF_FUSED_PROLOGUE);
         src = dst;
+        // one event pair around the n - 1 passes of a kind, one around the last
+        a = n > 1 ? prof_begin(c) : nullptr;
         for (int it = 0; it < n; ++it) {
             dst = 1 - src;
             const bool last = (it == n - 1);
-            a = prof_begin(c);
+            if (last) {
+                prof_end(c, a, PIXVOD_PROF_FUSED_ITERATE, n - 1);
+                a = prof_begin(c);
+            }
             HIP_TRY(c, launch_tree_iterate(g, c->tg, s, in, c->X[src], c->NX[src], c->X[dst], c->NX[dst], last,
                                            c->var_ll, c->valid, c->health, c->stream));
-            prof_end(c, a, last ? PIXVOD_PROF_FUSED_FINAL : PIXVOD_PROF_FUSED_ITERATE);
             src = dst;
         }
+        prof_end(c, a, PIXVOD_PROF_FUSED_FINAL);
         c->cur = src;
     } else if (c->schedule == PIXVOD_SCHED_PER_FACTOR) {
         const size_t pl = (size_t)c->plane;
@@ -658,30 +688,174 @@ static int run_iterations(pixvod_ctx* c, int n) {
             int rc = dev_alloc(c, &c->msg, pl * 116);
             if (rc) return rc;
         }
-        for (int it = 0; it < n; ++it) {
-            hipEvent_t a = prof_begin(c);
+        hipEvent_t a = prof_begin(c);
+        for (int it = 0; it < n; ++it)
             HIP_TRY(c, launch_pf_iteration(g, s, in, c->X[c->cur], c->marg, c->msg, c->var_ll, c->valid,
                                            c->P.damping, c->health, c->stream));
-            prof_end(c, a, PIXVOD_PROF_PER_FACTOR);
-        }
+        prof_end(c, a, PIXVOD_PROF_PER_FACTOR, n);
     } else {
         int src = c->cur, dst = 1 - c->cur;
         hipEvent_t a = prof_begin(c);
         HIP_TRY(c, launch_fu_prologue(g, s, in, c->X[src], c->X[dst], c->health, c->stream));
         prof_end(c, a, PIXVOD_PROF_FUSED_PROLOGUE);
         src = dst;
+        a = n > 1 ? prof_begin(c) : nullptr;
         for (int it = 0; it < n; ++it) {
             dst = 1 - src;
             const bool last = (it == n - 1);
-            a = prof_begin(c);
+            if (last) {
+                prof_end(c, a, PIXVOD_PROF_FUSED_ITERATE, n - 1);
+                a = prof_begin(c);
+            }
             HIP_TRY(c, launch_fu_iterate(g, s, in, c->X[src], c->X[dst], last, c->var_ll, c->valid,
                                          c->health, c->stream));
-            prof_end(c, a, last ? PIXVOD_PROF_FUSED_FINAL : PIXVOD_PROF_FUSED_ITERATE);
             src = dst;
         }
+        prof_end(c, a, PIXVOD_PROF_FUSED_FINAL);
         c->cur = src;
     }
     c->have_var = true;
+    return PIXVOD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the fused grid schedule's frame step as a replayed HIP graph: health word
+// cleared, prologue, n passes, frame reductions (one graph per starting buffer)
+
+static void key_bytes(std::vector<unsigned char>& k, const void* p, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    k.insert(k.end(), b, b + n);
+}
+#define key_put(k, v) key_bytes((k), &(v), sizeof(v))
+
+// the bytes of every argument the captured launches take (field by field, so
+// that struct padding plays no part): a graph is replayed only while they are
+// unchanged
+static std::vector<unsigned char> track_graph_key(const pixvod_ctx* c, int n_iters) {
+    std::vector<unsigned char> k;
+    const Geo g = geo_of(c);
+    key_put(k, g.H);
+    key_put(k, g.W);
+    key_put(k, g.pitch);
+    key_put(k, g.plane);
+    key_put(k, g.fx);
+    key_put(k, g.fy);
+    key_put(k, g.cx);
+    key_put(k, g.cy);
+    const Strengths s = strengths_of(c);
+    key_put(k, s.lamP);
+    key_put(k, s.lamR);
+    key_put(k, s.lamN);
+    key_put(k, s.lamD);
+    key_put(k, s.inv_sigD);
+    key_put(k, s.huber_k);
+    key_put(k, s.prior_ell);
+    key_put(k, s.prior_R);
+    key_put(k, s.prior_t);
+    key_put(k, s.prior_is_identity);
+    key_put(k, s.has_sigma_map);
+    key_put(k, s.has_prior_map);
+    const Inputs in = inputs_of(c);
+    const void* ptrs[] = {in.Is,     in.cxt,   in.cyt,      in.sigD,   in.It,     in.Gx,       in.Gy,
+                          in.prior_ell, c->X[0], c->X[1], c->var_ll, c->valid, c->health, c->partial,
+                          c->result};
+    key_put(k, ptrs);
+    key_put(k, n_iters);
+    key_put(k, c->prof);
+    return k;
+}
+#undef key_put
+
+static int track_graph_capture(pixvod_ctx* c, pixvod_ctx::TrackGraph& t, int src, int n_iters, bool events) {
+    const Geo g = geo_of(c);
+    const Strengths s = strengths_of(c);
+    const Inputs in = inputs_of(c);
+    const size_t n_ev = events ? 6 : 0;
+    while (t.ev.size() < n_ev) {
+        hipEvent_t e = nullptr;
+        HIP_TRY(c, hipEventCreate(&e));
+        t.ev.push_back(e);
+    }
+    t.kind.clear();
+    t.launches.clear();
+    HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = launch_set_ints(c->health, 1, 0, c->stream);
+    size_t e = 0;
+    auto mark = [&]() {
+        if (events && le == hipSuccess) le = hipEventRecordWithFlags(t.ev[e++], c->stream, hipEventRecordExternal);
+    };
+    // an event pair around the prologue, the n - 1 passes and the last pass
+    mark();
+    if (le == hipSuccess) le = launch_fu_prologue(g, s, in, c->X[src], c->X[1 - src], c->health, c->stream);
+    mark();
+    t.kind.push_back(PIXVOD_PROF_FUSED_PROLOGUE);
+    t.launches.push_back(1);
+    int cur = 1 - src;
+    if (n_iters > 1) mark();
+    for (int it = 0; it < n_iters; ++it) {
+        const bool last = (it == n_iters - 1);
+        if (last && n_iters > 1) {
+            mark();
+            t.kind.push_back(PIXVOD_PROF_FUSED_ITERATE);
+            t.launches.push_back(n_iters - 1);
+        }
+        if (last) mark();
+        if (le == hipSuccess)
+            le = launch_fu_iterate(g, s, in, c->X[cur], c->X[1 - cur], last, c->var_ll, c->valid, c->health,
+                                   c->stream);
+        cur = 1 - cur;
+    }
+    mark();
+    t.kind.push_back(PIXVOD_PROF_FUSED_FINAL);
+    t.launches.push_back(1);
+    if (le == hipSuccess) le = launch_frame_stats(g, c->X[cur], c->valid, 1, c->partial, c->result, c->stream);
+    hipGraph_t gr = nullptr;
+    const hipError_t ce = hipStreamEndCapture(c->stream, &gr);
+    if (le != hipSuccess || ce != hipSuccess) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return fail(c, PIXVOD_EHIP, std::string("frame step capture failed: ") +
+                                        hipGetErrorString(le != hipSuccess ? le : ce));
+    }
+    const hipError_t ie = hipGraphInstantiate(&t.exec, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (ie != hipSuccess) {
+        t.exec = nullptr;
+        return fail(c, PIXVOD_EHIP, std::string("frame step instantiation failed: ") + hipGetErrorString(ie));
+    }
+    return PIXVOD_OK;
+}
+
+// one frame step by graph replay; *used = false when it fell back to
+// run_iterations (profiling without capturable event nodes)
+static int track_graph_run(pixvod_ctx* c, int n_iters, bool* used) {
+    *used = false;
+    if (c->prof && !c->graph_events_ok) return PIXVOD_OK;
+    pixvod_ctx::TrackGraph& t = c->tgraph[c->cur];
+    std::vector<unsigned char> key = track_graph_key(c, n_iters);
+    if (!t.exec || t.key != key) {
+        if (t.exec) {
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            (void)hipGraphExecDestroy(t.exec);
+            t.exec = nullptr;
+        }
+        t.key.clear();
+        int rc = track_graph_capture(c, t, c->cur, n_iters, c->prof);
+        if (rc && c->prof) {
+            // event nodes not capturable here: profiled frames run unrolled
+            c->graph_events_ok = false;
+            (void)hipGetLastError();
+            return PIXVOD_OK;
+        }
+        if (rc) return rc;
+        t.key.swap(key);
+    }
+    HIP_TRY(c, hipGraphLaunch(t.exec, c->stream));
+    if (c->prof)
+        for (size_t i = 0; i < t.kind.size(); ++i)
+            c->graph_pending.push_back({t.ev[2 * i], t.ev[2 * i + 1], t.kind[i], t.launches[i]});
+    c->cur ^= (n_iters + 1) & 1;
+    c->have_var = true;
+    *used = true;
     return PIXVOD_OK;
 }
 
@@ -704,15 +878,22 @@ int pixvod_track(pixvod_ctx* c, const float* frame, int where, int n_iters, pixv
     const size_t N = (size_t)c->H * c->W;
     int rc = stage_frame(c, frame, where);
     if (rc) return rc;
-    HIP_TRY(c, hipMemsetAsync(c->health, 0, sizeof(int), c->stream));
-    if (n_iters == 0) {
-        HIP_TRY(c, launch_valid_only(g, strengths_of(c), inputs_of(c), c->X[c->cur], c->valid, c->stream));
-        c->have_var = false;
-    } else {
-        rc = run_iterations(c, n_iters);
+    bool graphed = false;
+    if (c->use_graph && n_iters > 0 && c->schedule == PIXVOD_SCHED_FUSED && c->topology == PIXVOD_TOPO_GRID) {
+        rc = track_graph_run(c, n_iters, &graphed);
         if (rc) return rc;
     }
-    HIP_TRY(c, launch_frame_stats(g, c->X[c->cur], c->valid, 1, c->partial, c->result, c->stream));
+    if (!graphed) {
+        HIP_TRY(c, hipMemsetAsync(c->health, 0, sizeof(int), c->stream));
+        if (n_iters == 0) {
+            HIP_TRY(c, launch_valid_only(g, strengths_of(c), inputs_of(c), c->X[c->cur], c->valid, c->stream));
+            c->have_var = false;
+        } else {
+            rc = run_iterations(c, n_iters);
+            if (rc) return rc;
+        }
+        HIP_TRY(c, launch_frame_stats(g, c->X[c->cur], c->valid, 1, c->partial, c->result, c->stream));
+    }
     if (out->inv_depth || out->inv_depth_var) {
         float* d_inv = out->inv_depth;
         float* d_var = out->inv_depth_var;
@@ -733,7 +914,7 @@ int pixvod_track(pixvod_ctx* c, const float* frame, int where, int n_iters, pixv
     HIP_TRY(c, hipMemcpyAsync(c->h_result, c->result, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->h_health, c->health, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    if (!c->pending.empty()) prof_collect(c);
+    if (!c->pending.empty() || !c->graph_pending.empty()) prof_collect(c);
 
     const double inv_n = 1.0 / (double)N;
     for (int k = 0; k < 6; ++k) {
@@ -760,6 +941,12 @@ int pixvod_track(pixvod_ctx* c, const float* frame, int where, int n_iters, pixv
 int pixvod_profile_enable(pixvod_ctx* c, int enable) {
     if (!c) return fail(nullptr, PIXVOD_EINVAL, "ctx is NULL");
     c->prof = enable != 0;
+    return PIXVOD_OK;
+}
+
+int pixvod_set_graph(pixvod_ctx* c, int enable) {
+    if (!c) return fail(nullptr, PIXVOD_EINVAL, "ctx is NULL");
+    c->use_graph = enable != 0;
     return PIXVOD_OK;
 }
 

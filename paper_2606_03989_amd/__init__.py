@@ -109,6 +109,7 @@ _SIGNATURES = {
     "pixvod_unroll_destroy": (C.c_int, [C.c_void_p]),
     "pixvod_unroll_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pixvod_unroll_set_keyframe": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "pixvod_unroll_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "pixvod_unroll_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_double,
                                         C.c_double, C.c_void_p, C.c_void_p, C.c_int]),
     "pixvod_unroll_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int,
@@ -537,6 +538,13 @@ class Unrolled(_FollowsTorchStream):
             raise ValueError("image and normals must live in the same memory")
         self._follow_torch(wi)
         _batch_check(lib().pixvod_unroll_set_keyframe(self._h, C.c_void_p(pi), C.c_void_p(pn), wi))
+
+    def set_state(self, state):
+        """The state the forward passes start from, in the exchange layout of
+        Tracker.get_state (123 x H x W float32)."""
+        ps, ws, ks = _ptr(state)
+        self._follow_torch(ws)
+        _batch_check(lib().pixvod_unroll_set_state(self._h, C.c_void_p(ps), ws))
 
     def forward(self, frames, sigma_map, sigma_N: float, huber_k: float, out_device: bool = False):
         """frames (F, H, W) float32; returns xi (F, 6) float64 numpy and the

@@ -441,71 +441,84 @@ __device__ inline PixelInputs load_pixel_inputs(const Geo& g, const Strengths& s
     return r;
 }
 
-// Adds the photometric factor of pixel (u, v) (Eq. distrb_photo, warp of
-// Eq. warp, Huber covariance weighting) and the prior factor (Eq. prior) at
-// the linearisation point (R, t) = Exp(tau), ell to (L, eta). Returns the
-// valid-warp flag.
-__device__ inline bool unary_factors(const Geo& g, const Strengths& s, const Inputs& in, int u, int v,
-                                     const double tau[6], const double R[9], const double t[3],
-                                     double ell, const PixelInputs& pin, double L[28], double eta[7]) {
-#pragma unroll
-    for (int k = 0; k < 28; ++k) L[k] = 0.0;
-#pragma unroll
-    for (int k = 0; k < 7; ++k) eta[k] = 0.0;
+// The photometric factor of pixel (u, v) (Eq. distrb_photo, warp of Eq. warp,
+// Huber covariance weighting) at the linearisation point (R, t) = Exp(tau),
+// ell, as the pieces that enter a belief: the 1 x 7 Jacobian J, the weight
+// w = kappa lamD and the residual r; valid is the valid-warp flag (an invalid
+// warp leaves the factor out).
+struct Photo {
+    double J[7];
+    double w, r;
+    bool valid;
+};
 
-    // --- photometric
+__device__ inline Photo photometric(const Geo& g, const Strengths& s, const Inputs& in, int u, int v,
+                                    const double R[9], const double t[3], double ell, const PixelInputs& pin) {
+    Photo f;
+    f.valid = false;
+    f.w = 0.0;
+    f.r = 0.0;
+#pragma unroll
+    for (int a = 0; a < 7; ++a) f.J[a] = 0.0;
     const double q0 = ((double)u - g.cx) / g.fx, q1 = ((double)v - g.cy) / g.fy;
     const double rho = exp(-ell);
     const double a0 = R[0] * q0 + R[1] * q1 + R[2] + rho * t[0];
     const double a1 = R[3] * q0 + R[4] * q1 + R[5] + rho * t[1];
     const double a2 = R[6] * q0 + R[7] * q1 + R[8] + rho * t[2];
-    bool valid = false;
     if (a2 > 0.0) {
         const double iz = rcp_nr(a2);
         const double wx = g.fx * a0 * iz + g.cx, wy = g.fy * a1 * iz + g.cy;
         if (wx >= -WARP_EPS && wx <= (g.W - 1) + WARP_EPS && wy >= -WARP_EPS && wy <= (g.H - 1) + WARP_EPS) {
-            valid = true;
+            f.valid = true;
             const double x = fmin(fmax(wx, 0.0), (double)(g.W - 1));
             const double y = fmin(fmax(wy, 0.0), (double)(g.H - 1));
             double It, gx, gy;
             sample3(in, g, x, y, It, gx, gy);
-            const double r = (double)pin.Is - It;
+            f.r = (double)pin.Is - It;
             // c = -g^T dw/da  (row 3-vector)
             const double c0 = -gx * g.fx * iz, c1 = -gy * g.fy * iz;
             const double c2 = (gx * g.fx * a0 + gy * g.fy * a1) * iz * iz;
-            // J_theta = c * (-R [q]x) = -(R^T c) x q ... computed as (R^T c) cross-form:
-            // -R[q]x d = -R (q x d)  => c.(-R (q x d)) = -(R^T c).(q x d) = -((R^T c) x ... )
-            const double b0 = R[0] * c0 + R[3] * c1 + R[6] * c2;   // R^T c
+            // J_theta = c.(-R [q]x d) = -(R^T c).(q x d) = -((R^T c) x q).d with b = R^T c
+            const double b0 = R[0] * c0 + R[3] * c1 + R[6] * c2;
             const double b1 = R[1] * c0 + R[4] * c1 + R[7] * c2;
             const double b2 = R[2] * c0 + R[5] * c1 + R[8] * c2;
-            // c.(-R (q x d)) = -b.(q x d) = -(b x q).d ... b.(q x d) = d.(b x q)
-            double J[7];
-            J[0] = -(b1 * 1.0 - b2 * q1);
-            J[1] = -(b2 * q0 - b0 * 1.0);
-            J[2] = -(b0 * q1 - b1 * q0);
-            J[3] = rho * b0;
-            J[4] = rho * b1;
-            J[5] = rho * b2;
-            J[6] = -rho * (c0 * t[0] + c1 * t[1] + c2 * t[2]);
+            f.J[0] = -(b1 * 1.0 - b2 * q1);
+            f.J[1] = -(b2 * q0 - b0 * 1.0);
+            f.J[2] = -(b0 * q1 - b1 * q0);
+            f.J[3] = rho * b0;
+            f.J[4] = rho * b1;
+            f.J[5] = rho * b2;
+            f.J[6] = -rho * (c0 * t[0] + c1 * t[1] + c2 * t[2]);
             const double isig = s.has_sigma_map ? rcp_nr((double)pin.sigD) : s.inv_sigD;
             const double lamD = isig * isig;
-            const double M = fabs(r) * isig;
+            const double M = fabs(f.r) * isig;
             double kappa = 1.0;
             if (M > s.huber_k) {
                 const double iM = rcp_nr(M);
                 kappa = s.huber_k * iM * (2.0 - s.huber_k * iM);
             }
-            const double w = kappa * lamD;
-#pragma unroll
-            for (int a = 0; a < 7; ++a) {
-                const double wJa = w * J[a];
-                eta[a] -= wJa * r;
-#pragma unroll
-                for (int b = a; b < 7; ++b) L[s7(a, b)] += wJa * J[b];
-            }
+            f.w = kappa * lamD;
         }
     }
+    return f;
+}
 
+// L += w J^T J, eta -= w J r for a valid photometric factor
+__device__ inline void add_photometric(const Photo& f, double L[28], double eta[7]) {
+    if (!f.valid) return;
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+        const double wJa = f.w * f.J[a];
+        eta[a] -= wJa * f.r;
+#pragma unroll
+        for (int b = a; b < 7; ++b) L[s7(a, b)] += wJa * f.J[b];
+    }
+}
+
+// Adds the prior factor (Eq. prior) at the linearisation point tau,
+// (R, t) = Exp(tau), ell to (L, eta).
+__device__ inline void add_prior(const Strengths& s, const double tau[6], const double R[9], const double t[3],
+                                 double ell, const PixelInputs& pin, double L[28], double eta[7]) {
     // --- prior: r = [Log(Exp(prior)^-1 Exp(tau)); ell - prior_ell],
     //     J = blockdiag(I + ad/2 + ad^2/12, 1)
     double rp[6];
@@ -574,7 +587,28 @@ __device__ inline bool unary_factors(const Geo& g, const Strengths& s, const Inp
     const double pell = s.has_prior_map ? (double)pin.prior_ell : s.prior_ell;
     eta[6] -= lamP * (ell - pell);
     L[s7(6, 6)] += lamP;
-    return valid;
+}
+
+// the unary belief (photometric + prior) from a photometric factor's pieces
+__device__ inline void unary_from(const Strengths& s, const Photo& f, const double tau[6], const double R[9],
+                                  const double t[3], double ell, const PixelInputs& pin, double L[28],
+                                  double eta[7]) {
+#pragma unroll
+    for (int k = 0; k < 28; ++k) L[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) eta[k] = 0.0;
+    add_photometric(f, L, eta);
+    add_prior(s, tau, R, t, ell, pin, L, eta);
+}
+
+// (L, eta) = photometric + prior factors of pixel (u, v) at tau, ell; returns
+// the valid-warp flag
+__device__ inline bool unary_factors(const Geo& g, const Strengths& s, const Inputs& in, int u, int v,
+                                     const double tau[6], const double R[9], const double t[3],
+                                     double ell, const PixelInputs& pin, double L[28], double eta[7]) {
+    const Photo f = photometric(g, s, in, u, v, R, t, ell, pin);
+    unary_from(s, f, tau, R, t, ell, pin, L, eta);
+    return f.valid;
 }
 
 __device__ inline bool unary_factors(const Geo& g, const Strengths& s, const Inputs& in, int u, int v,

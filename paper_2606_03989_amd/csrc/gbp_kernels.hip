@@ -440,7 +440,8 @@ __device__ __attribute__((always_inline)) inline void prologue_pixel(const Geo& 
     double tau[6], ell, R[9], t[3], L[28], eta[7];
     load_point(X, g, p, tau, ell);
     se3_exp(tau, R, t);
-    unary_factors(g, s, in, u, v, tau, R, t, ell, L, eta);
+    const PixelInputs pin = load_pixel_inputs(g, s, in, u, v);
+    unary_factors(g, s, in, u, v, tau, R, t, ell, pin, L, eta);
     float mid[4][27], mn[4][2];
     load_messages(X, g, p, mid, mn);
     add_messages(L, eta, mid, mn);

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/pixvod.h"
 #include "gbp_adjoint.h"
@@ -44,6 +45,14 @@ struct pixvod_unroll {
     float *X0 = nullptr, *Xw[2] = {nullptr, nullptr}, *tape = nullptr, *Xend = nullptr, *seg = nullptr;
     float *var_ll = nullptr, *valid = nullptr;
     double *marg = nullptr, *M = nullptr, *bel = nullptr, *Mb = nullptr, *Ub = nullptr, *Eb = nullptr;
+    // the reverse sweep recomputes the next segment on a side stream while
+    // the current one is reversed: a second set of recompute buffers (and of
+    // frame-prep planes, for segments of the next frame)
+    float *seg2 = nullptr, *tmp2 = nullptr, *sink2 = nullptr, *It2 = nullptr, *Gx2 = nullptr, *Gy2 = nullptr;
+    double *marg2 = nullptr, *M2 = nullptr, *bel2 = nullptr;
+    hipStream_t side = nullptr;
+    std::vector<hipEvent_t> evs;      // two per segment of a reverse sweep
+
     float* Xb[2] = {nullptr, nullptr};
     double *gsig = nullptr, *gN = nullptr, *gk = nullptr;
     double *partial = nullptr, *stats = nullptr, *h_stats = nullptr;
@@ -121,12 +130,15 @@ static bool ualloc(T** p, size_t n) {
 static void urelease(pixvod_unroll* u) {
     void* bufs[] = {u->Is, u->cxt, u->cyt, u->sig, u->It, u->Gx, u->Gy, u->frames, u->stage, u->X0, u->Xw[0],
                     u->Xw[1], u->tape, u->Xend, u->seg, u->var_ll, u->valid, u->marg, u->M, u->bel, u->Mb, u->Ub, u->Eb,
+                    u->seg2, u->tmp2, u->sink2, u->It2, u->Gx2, u->Gy2, u->marg2, u->M2, u->bel2,
                     u->Xb[0], u->Xb[1], u->gsig, u->gN, u->gk, u->partial, u->stats, u->health};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (u->h_stats) (void)hipHostFree(u->h_stats);
     for (hipEvent_t e : u->ev)
         if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : u->evs) (void)hipEventDestroy(e);
+    if (u->side) (void)hipStreamDestroy(u->side);
     if (u->own_stream) (void)hipStreamDestroy(u->own_stream);
 }
 
@@ -207,10 +219,16 @@ int pixvod_unroll_create(int H, int W, const pixvod_intrinsics* K, const pixvod_
               ualloc(&u->Mb, pl * MSG_PLANES) && ualloc(&u->Ub, pl * UB_PLANES) && ualloc(&u->Eb, pl * EB_PLANES) &&
               ualloc(&u->Xb[0], S) && ualloc(&u->Xb[1], S) && ualloc(&u->gsig, pl) && ualloc(&u->gN, pl) &&
               ualloc(&u->gk, pl) && ualloc(&u->partial, (size_t)nb * 8) &&
+              ualloc(&u->seg2, S * (size_t)ckpt_every) && ualloc(&u->tmp2, S) && ualloc(&u->sink2, S) &&
+              ualloc(&u->It2, pl) && ualloc(&u->Gx2, pl) && ualloc(&u->Gy2, pl) &&
+              ualloc(&u->marg2, pl * MARG_PLANES * (size_t)ckpt_every) &&
+              ualloc(&u->M2, pl * MSG_PLANES * (size_t)ckpt_every) &&
+              ualloc(&u->bel2, pl * BEL_PLANES * (size_t)ckpt_every) &&
               ualloc(&u->stats, (size_t)max_frames * 8 + 8) && ualloc(&u->health, 1);
     if (ok) ok = hipHostMalloc((void**)&u->h_stats, ((size_t)max_frames * 8 + 8) * sizeof(double)) == hipSuccess;
     for (int k = 0; ok && k < 4; ++k) ok = hipEventCreate(&u->ev[k]) == hipSuccess;
     if (ok) ok = hipStreamCreateWithFlags(&u->own_stream, hipStreamNonBlocking) == hipSuccess;
+    if (ok) ok = hipStreamCreateWithFlags(&u->side, hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
         urelease(u);
         delete u;
@@ -260,6 +278,24 @@ int pixvod_unroll_set_keyframe(pixvod_unroll* u, const float* img, const float* 
     UHIP(launch_keyframe_prep(g, u->stage, u->stage + N, u->Is, u->cxt, u->cyt, u->X0, u->Xw[0], u->stream));
     UHIP(hipStreamSynchronize(u->stream));
     u->have_kf = true;
+    u->n_fwd = 0;
+    return PIXVOD_OK;
+}
+
+int pixvod_unroll_set_state(pixvod_unroll* u, const float* state, int where) {
+    if (!u) return ufail(PIXVOD_EINVAL, "unroll is NULL");
+    if (!state) return ufail(PIXVOD_EINVAL, "state is NULL");
+    if (where != PIXVOD_HOST && where != PIXVOD_DEVICE) return ufail(PIXVOD_EINVAL, "bad location");
+    if (!u->have_kf) return ufail(PIXVOD_ESTATE, "pixvod_unroll_set_state before pixvod_unroll_set_keyframe");
+    const size_t S = state_floats(u);
+    const float* d = state;
+    if (where == PIXVOD_HOST) {
+        // staged through the first work buffer, which no forward pass needs kept
+        UHIP(hipMemcpyAsync(u->Xw[1], state, S * sizeof(float), hipMemcpyHostToDevice, u->stream));
+        d = u->Xw[1];
+    }
+    UHIP(launch_pack_state(ugeo(u), u->X0, const_cast<float*>(d), 0, u->stream));
+    UHIP(hipStreamSynchronize(u->stream));
     u->n_fwd = 0;
     return PIXVOD_OK;
 }
@@ -346,46 +382,99 @@ int pixvod_unroll_backward(pixvod_unroll* u, const double* xi_bar, const float* 
     UHIP(hipMemsetAsync(u->gsig, 0, pl * sizeof(double), u->stream));
     UHIP(hipMemsetAsync(u->gN, 0, pl * sizeof(double), u->stream));
     UHIP(hipMemsetAsync(u->gk, 0, pl * sizeof(double), u->stream));
+
+    // Segments in reverse order, item i = (frame f, segment sg). Item i is
+    // recomputed on the side stream into buffer set i % 2 (frame-prep planes
+    // of set f % 2) while the main stream reverses item i - 1: recompute i
+    // waits for the reversal of item i - 2, the previous user of both sets,
+    // and reversal i waits for recompute i.
+    const int S_ = u->seg_per_frame, T = F * S_;
+    struct Set {
+        float *seg, *tmp, *sink;
+        double *marg, *M, *bel;
+    };
+    const Set sets[2] = {{u->seg, u->Xw[0], u->Xw[1], u->marg, u->M, u->bel},
+                         {u->seg2, u->tmp2, u->sink2, u->marg2, u->M2, u->bel2}};
+    Inputs ins[2] = {in, in};
+    ins[1].It = u->It2;
+    ins[1].Gx = u->Gx2;
+    ins[1].Gy = u->Gy2;
+    while ((int)u->evs.size() < 2 * T + 1) {
+        hipEvent_t e = nullptr;
+        UHIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        u->evs.push_back(e);
+    }
+    hipEvent_t* evC = u->evs.data();          // recompute i done
+    hipEvent_t* evR = u->evs.data() + T;      // reversal i done
+    hipEvent_t ev_start = u->evs[2 * T];
+    // the side stream starts after everything queued on the main stream
+    UHIP(hipEventRecord(ev_start, u->stream));
+    UHIP(hipStreamWaitEvent(u->side, ev_start, 0));
+
+    auto item_f = [&](int i) { return F - 1 - i / S_; };
+    auto item_sg = [&](int i) { return S_ - 1 - i % S_; };
+    auto recompute = [&](int i) -> int {
+        const int f = item_f(i), sg = item_sg(i);
+        const Set& B = sets[i & 1];
+        const Inputs& I = ins[f & 1];
+        if (i >= 2) UHIP(hipStreamWaitEvent(u->side, evR[i - 2], 0));
+        if (sg == S_ - 1)
+            UHIP(launch_frame_prep(g, u->frames + N * f, u->W, const_cast<float*>(I.It), const_cast<float*>(I.Gx),
+                                   const_cast<float*>(I.Gy), u->side));
+        // states of the segment: seg[0] = checkpoint, seg[i] after i
+        // iterations; each recompute step also keeps the marginals and the
+        // new messages of its source state (the last step's result is not
+        // needed and goes to a work buffer)
+        const int len = seg_len(u, sg);
+        UHIP(hipMemcpyAsync(B.seg, ckpt(u, f, sg), S * sizeof(float), hipMemcpyDeviceToDevice, u->side));
+        for (int k = 0; k < len; ++k) {
+            float* dst = (k + 1 < len) ? B.seg + S * (k + 1) : B.sink;
+            UHIP(launch_fu_step_tape(g, s, I, B.seg + S * k, B.tmp, dst, B.marg + pl * MARG_PLANES * k,
+                                     B.M + pl * MSG_PLANES * k, B.bel + pl * BEL_PLANES * k, u->var_ll, u->valid,
+                                     u->health, u->side));
+        }
+        UHIP(hipEventRecord(evC[i], u->side));
+        return PIXVOD_OK;
+    };
+
     int cur = 0;
-    for (int f = F - 1; f >= 0; --f) {
-        const float* xend = (f == F - 1) ? u->Xend : ckpt(u, f + 1, 0);
-        PoseBar xb;
-        for (int k = 0; k < 6; ++k) xb.v[k] = xi_bar ? xi_bar[6 * f + k] / (double)N : 0.0;
-        const float* rb = nullptr;
-        if (inv_depth_bar && where == PIXVOD_HOST) {
-            UHIP(hipMemcpyAsync(rho_stage, inv_depth_bar + N * f, N * sizeof(float), hipMemcpyHostToDevice,
-                                u->stream));
-            rb = rho_stage;
-        } else if (inv_depth_bar) {
-            rb = inv_depth_bar + N * f;
+    int rc = recompute(0);
+    if (rc) return rc;
+    for (int i = 0; i < T; ++i) {
+        if (i + 1 < T) {
+            rc = recompute(i + 1);
+            if (rc) return rc;
         }
-        UHIP(launch_adj_inject(g, xend, u->Xb[cur], xb, rb, u->stream));
-        UHIP(launch_frame_prep(g, u->frames + N * f, u->W, u->It, u->Gx, u->Gy, u->stream));
-        for (int sg = u->seg_per_frame - 1; sg >= 0; --sg) {
-            const int len = seg_len(u, sg);
-            // states of the segment: seg[0] = checkpoint, seg[i] after i
-            // iterations; each recompute step also keeps the marginals and the
-            // new messages of its source state (the last step's result is not
-            // needed and goes to a work buffer)
-            UHIP(hipMemcpyAsync(u->seg, ckpt(u, f, sg), S * sizeof(float), hipMemcpyDeviceToDevice, u->stream));
-            for (int i = 0; i < len; ++i) {
-                float* dst = (i + 1 < len) ? u->seg + S * (i + 1) : u->Xw[1];
-                UHIP(launch_fu_step_tape(g, s, in, u->seg + S * i, u->Xw[0], dst, u->marg + pl * MARG_PLANES * i,
-                                         u->M + pl * MSG_PLANES * i, u->bel + pl * BEL_PLANES * i, u->var_ll,
-                                         u->valid, u->health, u->stream));
+        const int f = item_f(i), sg = item_sg(i);
+        const Set& B = sets[i & 1];
+        const Inputs& I = ins[f & 1];
+        if (sg == S_ - 1) {
+            // the frame's output cotangents enter at its last state
+            const float* xend = (f == F - 1) ? u->Xend : ckpt(u, f + 1, 0);
+            PoseBar xb;
+            for (int k = 0; k < 6; ++k) xb.v[k] = xi_bar ? xi_bar[6 * f + k] / (double)N : 0.0;
+            const float* rb = nullptr;
+            if (inv_depth_bar && where == PIXVOD_HOST) {
+                UHIP(hipMemcpyAsync(rho_stage, inv_depth_bar + N * f, N * sizeof(float), hipMemcpyHostToDevice,
+                                    u->stream));
+                rb = rho_stage;
+            } else if (inv_depth_bar) {
+                rb = inv_depth_bar + N * f;
             }
-            for (int i = len - 1; i >= 0; --i) {
-                const float* X = u->seg + S * i;
-                const double* marg = u->marg + pl * MARG_PLANES * i;
-                const double* M = u->M + pl * MSG_PLANES * i;
-                const double* bel = u->bel + pl * BEL_PLANES * i;
-                UHIP(launch_adj_update(g, s, in, X, M, bel, u->Xb[cur], u->Mb, u->Ub, u->stream));
-                UHIP(launch_adj_edges(g, s, in, X, marg, M, u->Mb, u->Xb[cur ^ 1], u->Eb, u->gN, u->stream));
-                UHIP(launch_adj_belief(g, s, in, X, marg, u->Ub, u->Eb, u->Xb[cur ^ 1], u->gsig, u->gk,
-                                       u->stream));
-                cur ^= 1;
-            }
+            UHIP(launch_adj_inject(g, xend, u->Xb[cur], xb, rb, u->stream));
         }
+        UHIP(hipStreamWaitEvent(u->stream, evC[i], 0));
+        for (int k = seg_len(u, sg) - 1; k >= 0; --k) {
+            const float* X = B.seg + S * k;
+            const double* marg = B.marg + pl * MARG_PLANES * k;
+            const double* M = B.M + pl * MSG_PLANES * k;
+            const double* bel = B.bel + pl * BEL_PLANES * k;
+            UHIP(launch_adj_update(g, s, I, X, M, bel, u->Xb[cur], u->Mb, u->Ub, u->stream));
+            UHIP(launch_adj_edges(g, s, I, X, marg, M, u->Mb, u->Xb[cur ^ 1], u->Eb, u->gN, u->stream));
+            UHIP(launch_adj_belief(g, s, I, X, marg, u->Ub, u->Eb, u->Xb[cur ^ 1], u->gsig, u->gk, u->stream));
+            cur ^= 1;
+        }
+        UHIP(hipEventRecord(evR[i], u->stream));
     }
     UHIP(launch_sum2(g, u->gN, u->gk, u->partial, u->stats, u->stream));
     if (grad_sigma_map) {

@@ -56,3 +56,4 @@ def test_graph_replay_equals_unrolled_passes(profile):
         assert cref == [iters - n_tracks, n_tracks, n_tracks]
         assert cgot == cref
 
+

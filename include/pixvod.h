@@ -362,6 +362,14 @@ int pixvod_unroll_set_stream(pixvod_unroll* u, void* hip_stream);
 /* keyframe image (H*W) and normals (H*W*3), as pixvod_set_keyframe */
 int pixvod_unroll_set_keyframe(pixvod_unroll* u, const float* img, const float* normals, int where);
 
+/* Replaces the state the forward passes start from (after
+ * pixvod_unroll_set_keyframe, which resets it) with `state` in the exchange
+ * layout of pixvod_get_state (123 * H * W floats at `where`); the keyframe is
+ * kept. A forward pass from a given state makes the reverse sweep of a few
+ * iterations comparable with differences of the same iterations from the
+ * same state. PIXVOD_ESTATE before a keyframe. */
+int pixvod_unroll_set_state(pixvod_unroll* u, const float* state, int where);
+
 /* frames: n_frames * H * W (1 <= n_frames <= max_frames), copied; sigma_map:
  * H * W photometric sigmas (> 0); sigma_N > 0 and huber_k > 0 replace the
  * creation parameters. xi_out (host, n_frames * 6 doubles) and inv_depth_out

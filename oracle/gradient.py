@@ -9,7 +9,9 @@ output cotangents (cxi, crho) the scalar
     L = sum_f cxi[f] . xi[f] + sum_f sum_i crho[f, i] rho[f, i]
 is differentiated with respect to the photometric sigma map (Eq.
 distrb_photo), the normal-integration sigma (Eq. gbpni) and the Huber
-threshold by symmetric differences of relative step h.
+threshold by symmetric differences of relative step h. A run may start from
+a given state instead of the fresh keyframe state (teacher forcing: a few
+iterations from the same state on both sides of a comparison).
 """
 
 from __future__ import annotations
@@ -25,8 +27,9 @@ class UnrolledOracle:
     """Repeated unrolled runs of one workload with varying parameters."""
 
     def __init__(self, cam, I_s, N_s, frames, n_iters: int, sigma_map, sigma_N: float, huber_k: float,
-                 **cfg_kw):
+                 start=None, **cfg_kw):
         self.cam, self.I_s, self.N_s = cam, I_s, N_s
+        self.start = None if start is None else np.asarray(start, np.float64)
         self.frames = [np.asarray(f, np.float32) for f in frames]
         self.n_iters = int(n_iters)
         self.sigma_map = np.asarray(sigma_map, np.float64)
@@ -40,6 +43,8 @@ class UnrolledOracle:
         try:
             o.set_sigma_D_map(self.sigma_map if sigma_map is None else sigma_map)
             o.set_keyframe(self.I_s, self.N_s)
+            if self.start is not None:
+                o.set_state(self.start)
             xi, rho = [], []
             for f in self.frames:
                 r = o.track(f, self.n_iters)

@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 import torch
 
-from parity import diff_crop_workload, diff_full_workload, make_unroll, make_unrolled_oracle
+from parity import diff_crop_workload, diff_full_workload, from_oracle, make_unroll, make_unrolled_oracle, to_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -70,6 +70,57 @@ def test_full_size_directional_derivative():
            gk * dk * w["huber_k"])
     print(f"320x240 directional derivative: adjoint {add:.9e} oracle {fdd:.9e}", flush=True)
     assert abs(add - fdd) <= 5e-3 * abs(fdd)
+
+
+def test_teacher_forced_one_iteration_full_size():
+    # 320x240: both sides start from the oracle's state after ten iterations
+    # of frame 1 (rounded to the FP32 state) and run one iteration of frame 2;
+    # a single iteration is smooth in the parameters, so the reverse kernels
+    # meet the oracle's FP64 differences closely at full size
+    import oracle
+    from oracle.gradient import UnrolledOracle
+    w = diff_full_workload(2)
+    cam = w["cam"]
+    o = oracle.Oracle(oracle.config_for_camera(cam, sigma_N=w["sigma_N"], huber_k=w["huber_k"], **w["kw"]))
+    o.set_sigma_D_map(w["sigma_map"])
+    o.set_keyframe(w["I_s"], w["N_s"])
+    o.track(w["frames"][0], 10)
+    start32 = from_oracle(o.get_state())
+    o.close()
+    frame = w["frames"][1]
+    cxi, crho = w["cxi"][1:2], w["crho"][1:2]
+    u = make_unroll(dict(w, frames=[frame]), 1, 1)
+    u.set_state(start32)
+    xi, rho = u.forward(np.stack([frame]).astype(np.float32), w["sigma_map"], w["sigma_N"], w["huber_k"])
+    g, gN, gk = u.backward(cxi, crho)
+    u.close()
+    orc = UnrolledOracle(cam, w["I_s"], w["N_s"], [frame], 1, w["sigma_map"], w["sigma_N"], w["huber_k"],
+                         start=to_oracle(start32), **w["kw"])
+    out = orc.outputs()
+    dxi = np.abs(xi - out["xi"]).max()
+    print(f"one iteration from the oracle's state: pose {dxi:.2e}", flush=True)
+    assert dxi <= 1e-5
+    fN, fk = orc.d_sigma_N(cxi, crho), orc.d_huber_k(cxi, crho)
+    eN, ek = abs(gN - fN) / abs(fN), abs(gk - fk) / abs(fk)
+    print(f"sigma_N: adjoint {gN:.9e} differences {fN:.9e} (rel {eN:.1e}); "
+          f"huber_k: adjoint {gk:.9e} differences {fk:.9e} (rel {ek:.1e})", flush=True)
+    rng = np.random.default_rng(2)
+    entries = [tuple(x) for x in rng.integers(0, (cam.H, cam.W), size=(24, 2))]
+    fd = np.array([orc.d_sigma_entry(cxi, crho, v, u_) for v, u_ in entries])
+    ad = np.array([g[v, u_] for v, u_ in entries], np.float64)
+    scale = np.abs(fd).max()
+    err = np.abs(ad - fd)
+    print(f"sigma map: {len(entries)} entries, max |adj - fd| {err.max():.3e} of max |fd| {scale:.3e}", flush=True)
+    d = rng.uniform(-1.0, 1.0, (cam.H, cam.W))
+    dN, dk = 0.7, -0.4
+    fdd = orc.d_direction(cxi, crho, d, dN, dk)
+    add = (float(np.sum(g.astype(np.float64) * d * w["sigma_map"].astype(np.float64))) + gN * dN * w["sigma_N"] +
+           gk * dk * w["huber_k"])
+    edd = abs(add - fdd) / abs(fdd)
+    print(f"directional: adjoint {add:.9e} differences {fdd:.9e} (rel {edd:.1e})", flush=True)
+    assert eN <= 1e-4 and ek <= 1e-3
+    assert np.all(err <= 1e-4 * scale + 1e-4 * np.abs(fd))
+    assert edd <= 1e-4
 
 
 def test_checkpoint_interval_does_not_change_gradients():

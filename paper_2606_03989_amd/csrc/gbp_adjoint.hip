@@ -6,8 +6,9 @@
 // update + relinearise + transport; Sec. 3.4 and Sec. 4.1), given the
 // cotangent Xb' of X':
 //   forward recompute  the fused passes that recompute X also keep its belief
-//                      and marginals (64 planes), its new messages (116) and
-//                      the belief of the update (35);
+//                      and marginals (64 planes), the information of its new
+//                      messages (88 FP32 planes: exact, they are the FP32
+//                      partials' values) and the belief of the update (35);
 //   k_adj_update       reverse of the update at every pixel: cotangents of its
 //                      four new messages (Mb, 116 planes) and of its unary
 //                      information and point (Ub, 42 planes);
@@ -20,7 +21,12 @@
 //                      pixel are summed with lane shuffles);
 //   k_adj_belief       reverse of the marginals and of the unary factors:
 //                      completes Xb (cotangent of X) and accumulates the
-//                      per-pixel parameter gradients.
+//                      per-pixel parameter gradients. Every stored message
+//                      enters the belief the same way, so its cotangent
+//                      there is one 29-value slot-common part Cb per pixel;
+//                      it is kept apart from the slot-specific part in Xb
+//                      and added by the next reader (k_adj_update), instead
+//                      of a read-modify-write of all four slots.
 #include "gbp_adjoint.h"
 #include "gbp_adjoint.hpp"
 
@@ -45,9 +51,9 @@ __device__ inline bool pixel_2d(const Geo& g, int& u, int& v) {
 // reverse of the update (k_pf_update): belief from the unary and the new
 // messages, mean m, relinearisation, transport of the messages
 __global__ __launch_bounds__(256, 2) void k_adj_update(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
-                                                    const double* __restrict__ M, const double* __restrict__ bel,
-                                                    const float* __restrict__ Xb, double* __restrict__ Mb,
-                                                    double* __restrict__ Ub) {
+                                                    const float* __restrict__ M, const double* __restrict__ bel,
+                                                    const float* __restrict__ Xb, const float* __restrict__ Cb,
+                                                    double* __restrict__ Mb, double* __restrict__ Ub) {
     int u, v;
     if (!pixel_2d(g, u, v)) return;
     const long p = pix_of(g, u, v);
@@ -76,17 +82,18 @@ __global__ __launch_bounds__(256, 2) void k_adj_update(Geo g, Strengths s, Input
     for (int d = 0; d < 4; ++d) {
         int nu, nv;
         if (!neighbour(g, u, v, d, nu, nv)) continue;
-        const double* md = M + (long)d * MSG_STRIDE * pl + p;
+        const float* md = M + (long)d * LAM_STRIDE * pl + p;
         const float* xb = Xb + (long)(P_MID + d * MID_STRIDE) * pl + p;
+        const float* cb = Cb + p;
         double Lam[21], eb[6], y[6];
 #pragma unroll
-        for (int k = 0; k < 21; ++k) Lam[k] = md[(6 + k) * pl];
+        for (int k = 0; k < 21; ++k) Lam[k] = (double)md[k * pl];
 #pragma unroll
-        for (int a = 0; a < 6; ++a) eb[a] = (double)xb[a * pl];
+        for (int a = 0; a < 6; ++a) eb[a] = (double)xb[a * pl] + (double)cb[a * pl];
         sym_mv6(Lam, eb, y);
 #pragma unroll
         for (int a = 0; a < 6; ++a) mb[a] -= y[a];
-        mb[6] -= md[28 * pl] * (double)Xb[(long)(P_MN + 2 * d) * pl + p];
+        mb[6] -= (double)md[21 * pl] * ((double)Xb[(long)(P_MN + 2 * d) * pl + p] + (double)cb[27 * pl]);
     }
     // relinearisation tau' = Log(Exp(tau) Exp(m_p)):
     //   d tau' = Jl(tau')^-1 Jl(tau) d tau + Jr(tau')^-1 Jr(m_p) d m_p
@@ -121,10 +128,11 @@ __global__ __launch_bounds__(256, 2) void k_adj_update(Geo g, Strengths s, Input
             continue;
         }
         const float* xb = Xb + (long)(P_MID + d * MID_STRIDE) * pl + p;
+        const float* cb = Cb + p;
         double eb[6];
 #pragma unroll
         for (int a = 0; a < 6; ++a) {
-            eb[a] = (double)xb[a * pl];
+            eb[a] = (double)xb[a * pl] + (double)cb[a * pl];
             o[a * pl] = eb[a] + betab[a];
         }
 #pragma unroll
@@ -132,10 +140,11 @@ __global__ __launch_bounds__(256, 2) void k_adj_update(Geo g, Strengths s, Input
 #pragma unroll
             for (int c = r; c < 6; ++c) {
                 const double tr = (r == c) ? eb[r] * m[r] : eb[r] * m[c] + eb[c] * m[r];
-                o[(6 + s6(r, c)) * pl] = (double)xb[(6 + s6(r, c)) * pl] - tr + Bb[s7(r, c)];
+                o[(6 + s6(r, c)) * pl] =
+                    ((double)xb[(6 + s6(r, c)) * pl] + (double)cb[(6 + s6(r, c)) * pl]) - tr + Bb[s7(r, c)];
             }
-        const double neb = (double)Xb[(long)(P_MN + 2 * d) * pl + p];
-        const double nlb = (double)Xb[(long)(P_MN + 2 * d + 1) * pl + p];
+        const double neb = (double)Xb[(long)(P_MN + 2 * d) * pl + p] + (double)cb[27 * pl];
+        const double nlb = (double)Xb[(long)(P_MN + 2 * d + 1) * pl + p] + (double)cb[28 * pl];
         o[27 * pl] = neb + betab[6];
         o[28 * pl] = nlb - neb * m[6] + Bb[s7(6, 6)];
     }
@@ -157,7 +166,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_update(Geo g, Strengths s, Input
 // cotangents are summed with lane shuffles and written by the d = 0 lane.
 // Writes the sender part of j's slot-d cotangent to Xbo.
 __global__ __launch_bounds__(256) void k_adj_edges(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
-                                                   const double* __restrict__ marg, const double* __restrict__ M,
+                                                   const double* __restrict__ marg, const float* __restrict__ M,
                                                    const double* __restrict__ Mb, float* __restrict__ Xbo,
                                                    double* __restrict__ Eb, double* __restrict__ gN) {
     const int d = threadIdx.x & 3;
@@ -181,9 +190,9 @@ __global__ __launch_bounds__(256) void k_adj_edges(Geo g, Strengths s, Inputs in
         se3_exp(tau, R, t);
         const long pi = pix_of(g, nu, nv);
         const int o = opposite(d);
-        const double* Mj = M + (long)d * MSG_STRIDE * pl + pj;
+        const float* Mj = M + (long)d * LAM_STRIDE * pl + pj;
         const double* Mbj = Mb + (long)d * MSG_STRIDE * pl + pj;
-        const double* Mi = M + (long)o * MSG_STRIDE * pl + pi;
+        const float* Mi = M + (long)o * LAM_STRIDE * pl + pi;
         const double* Mbi = Mb + (long)o * MSG_STRIDE * pl + pi;
         // residual of the message into j from i, r = Log(Exp(tau_i)^-1 Exp(tau_j));
         // the message into i from j uses -r
@@ -197,12 +206,12 @@ __global__ __launch_bounds__(256) void k_adj_edges(Geo g, Strengths s, Inputs in
         {
             double Lam[21], e[6], y1[6], y2[6];
 #pragma unroll
-            for (int k = 0; k < 21; ++k) Lam[k] = Mj[(6 + k) * pl];
+            for (int k = 0; k < 21; ++k) Lam[k] = (double)Mj[k * pl];
 #pragma unroll
             for (int a = 0; a < 6; ++a) e[a] = Mbj[a * pl];
             sym_mv6(Lam, e, y1);
 #pragma unroll
-            for (int k = 0; k < 21; ++k) Lam[k] = Mi[(6 + k) * pl];
+            for (int k = 0; k < 21; ++k) Lam[k] = (double)Mi[k * pl];
 #pragma unroll
             for (int a = 0; a < 6; ++a) e[a] = Mbi[a * pl];
             sym_mv6(Lam, e, y2);
@@ -244,7 +253,7 @@ __global__ __launch_bounds__(256) void k_adj_edges(Geo g, Strengths s, Inputs in
         if (s.lamN > 0.0 && normal_residual(g, in, pj, pi, d, ell, elli, rn_j)) {
             normal_residual(g, in, pi, pj, o, elli, ell, rn_i);
             // ne_new = h - lp rn: receiver j and sender j (rn_i depends on ell_j with -1)
-            acc[35] = -Mj[28 * pl] * Mbj[27 * pl] + Mi[28 * pl] * Mbi[27 * pl];
+            acc[35] = -(double)Mj[21 * pl] * Mbj[27 * pl] + (double)Mi[21 * pl] * Mbi[27 * pl];
             const double neb = Mbi[27 * pl], nlb = Mbi[28 * pl];
             const double ls = marg[27L * pl + pj] - (double)X[(long)(P_MN + 2 * d + 1) * pl + pj];
             const double vs = marg[28L * pl + pj] - (double)X[(long)(P_MN + 2 * d) * pl + pj];
@@ -286,12 +295,13 @@ __global__ __launch_bounds__(256) void k_adj_edges(Geo g, Strengths s, Inputs in
     }
 }
 
-// reverse of the marginals and of the unary factors; completes Xbo
+// reverse of the marginals and of the unary factors; completes Xbo (point
+// planes) and writes the slot-common part Cbo
 __global__ __launch_bounds__(256) void k_adj_belief(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
                                                     const double* __restrict__ marg, const double* __restrict__ Ub,
                                                     const double* __restrict__ Eb,
-                                                    float* __restrict__ Xbo, double* __restrict__ gsig,
-                                                    double* __restrict__ gk) {
+                                                    float* __restrict__ Xbo, float* __restrict__ Cbo,
+                                                    double* __restrict__ gsig, double* __restrict__ gk) {
     int u, v;
     if (!pixel_2d(g, u, v)) return;
     const long p = pix_of(g, u, v);
@@ -336,23 +346,16 @@ __global__ __launch_bounds__(256) void k_adj_belief(Geo g, Strengths s, Inputs i
 #pragma unroll
     for (int k = 0; k < 6; ++k) Xbo[(long)(P_TAU + k) * pl + p] = (float)(taub[k] + te[k]);
     Xbo[(long)P_ELL * pl + p] = (float)ellb;
-    // every stored message enters the belief
+    // every stored message enters the belief: one slot-common cotangent
+    float* cb = Cbo + p;
 #pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        int nu, nv;
-        if (!neighbour(g, u, v, d, nu, nv)) continue;
-        float* xo = Xbo + (long)(P_MID + d * MID_STRIDE) * pl + p;
+    for (int a = 0; a < 6; ++a) cb[a * pl] = (float)ebS[a];
 #pragma unroll
-        for (int a = 0; a < 6; ++a) xo[a * pl] = (float)((double)xo[a * pl] + ebS[a]);
+    for (int r = 0; r < 6; ++r)
 #pragma unroll
-        for (int r = 0; r < 6; ++r)
-#pragma unroll
-            for (int c = r; c < 6; ++c)
-                xo[(6 + s6(r, c)) * pl] = (float)((double)xo[(6 + s6(r, c)) * pl] + BbS[s7(r, c)]);
-        float* xn = Xbo + (long)(P_MN + 2 * d) * pl + p;
-        xn[0] = (float)((double)xn[0] + ebS[6]);
-        xn[pl] = (float)((double)xn[pl] + BbS[s7(6, 6)]);
-    }
+        for (int c = r; c < 6; ++c) cb[(6 + s6(r, c)) * pl] = (float)BbS[s7(r, c)];
+    cb[27 * pl] = (float)ebS[6];
+    cb[28 * pl] = (float)BbS[s7(6, 6)];
     gsig[p] += sigb;
     gk[p] += kb;
 }
@@ -423,14 +426,15 @@ __global__ void k_plane_to_dense(Geo g, const double* __restrict__ src, float* _
 static const dim3 kAdjBlock(64, 4);
 static dim3 adj_grid(const Geo& g) { return dim3((g.W + 63) / 64, (g.H + 3) / 4); }
 
-hipError_t launch_adj_update(const Geo& g, const Strengths& s, const Inputs& in, const float* X, const double* M,
-                             const double* bel, const float* Xb, double* Mb, double* Ub, hipStream_t st) {
-    hipLaunchKernelGGL(k_adj_update, adj_grid(g), kAdjBlock, 0, st, g, s, in, X, M, bel, Xb, Mb, Ub);
+hipError_t launch_adj_update(const Geo& g, const Strengths& s, const Inputs& in, const float* X, const float* M,
+                             const double* bel, const float* Xb, const float* Cb, double* Mb, double* Ub,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_update, adj_grid(g), kAdjBlock, 0, st, g, s, in, X, M, bel, Xb, Cb, Mb, Ub);
     return hipGetLastError();
 }
 
 hipError_t launch_adj_edges(const Geo& g, const Strengths& s, const Inputs& in, const float* X, const double* marg,
-                            const double* M, const double* Mb, float* Xbo, double* Eb, double* gN, hipStream_t st) {
+                            const float* M, const double* Mb, float* Xbo, double* Eb, double* gN, hipStream_t st) {
     // one lane per (pixel, direction): 64 pixels of a row per 256-lane workgroup
     hipLaunchKernelGGL(k_adj_edges, dim3((g.W + 63) / 64, g.H), dim3(256), 0, st, g, s, in, X, marg, M, Mb, Xbo, Eb,
                        gN);
@@ -438,9 +442,9 @@ hipError_t launch_adj_edges(const Geo& g, const Strengths& s, const Inputs& in, 
 }
 
 hipError_t launch_adj_belief(const Geo& g, const Strengths& s, const Inputs& in, const float* X, const double* marg,
-                             const double* Ub, const double* Eb, float* Xbo, double* gsig, double* gk,
+                             const double* Ub, const double* Eb, float* Xbo, float* Cbo, double* gsig, double* gk,
                              hipStream_t st) {
-    hipLaunchKernelGGL(k_adj_belief, adj_grid(g), kAdjBlock, 0, st, g, s, in, X, marg, Ub, Eb, Xbo, gsig, gk);
+    hipLaunchKernelGGL(k_adj_belief, adj_grid(g), kAdjBlock, 0, st, g, s, in, X, marg, Ub, Eb, Xbo, Cbo, gsig, gk);
     return hipGetLastError();
 }
 

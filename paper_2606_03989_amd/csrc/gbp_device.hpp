@@ -21,6 +21,7 @@ constexpr int P_MID = 7;                 // 4 x 27: eta(6) + upper-packed Lambda
 constexpr int P_MN = 115;                // 4 x 2: eta, lambda
 constexpr int N_PLANES = 123;
 constexpr int MID_STRIDE = 27;
+constexpr int LAM_STRIDE = 22;           // reverse-sweep tape per slot: Lambda 21, normal lambda
 
 enum { DIR_L = 0, DIR_R = 1, DIR_U = 2, DIR_D = 3 };
 

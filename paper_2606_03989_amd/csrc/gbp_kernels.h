@@ -27,7 +27,7 @@ hipError_t launch_fu_iterate(const Geo& g, const Strengths& s, const Inputs& in,
 // FP64 planes) followed by the belief they come from (35), the new messages
 // (116) and the belief of the update, unary + new messages (35)
 hipError_t launch_fu_step_tape(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* tmp,
-                               float* Y, double* marg, double* M, double* bel, float* var_ll, float* valid,
+                               float* Y, double* marg, float* M, double* bel, float* var_ll, float* valid,
                                int* health, hipStream_t st);
 hipError_t launch_valid_only(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* valid,
                              hipStream_t st);

@@ -127,11 +127,14 @@ __device__ inline void accumulate_message(double L[28], double eta[7], const dou
 }
 
 // receiver side: completes the partial in slot d with the residual at both
-// linearisation points, eta = h - Lambda' r, and adds it to the belief
+// linearisation points, eta = h - Lambda' r, and adds it to the belief.
+// Lam_out (reverse-sweep tape) receives each new message's information (the
+// identity Lambda and the normal lambda, 22 FP32 planes per slot: they are
+// the partials' FP32 values, so the FP32 tape is exact)
 __device__ inline void complete_partials(const Geo& g, const Strengths& s, const Inputs& in,
                                          const float* __restrict__ X, int u, int v, const double R[9],
                                          const double t[3], double ell, double L[28], double eta[7],
-                                         float mid[4][27], float mn[4][2], double* __restrict__ M_out = nullptr) {
+                                         float mid[4][27], float mn[4][2], float* __restrict__ Lam_out = nullptr) {
     const long pi = pix_of(g, u, v);
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
@@ -140,9 +143,9 @@ __device__ inline void complete_partials(const Geo& g, const Strengths& s, const
 #pragma unroll
             for (int k = 0; k < 27; ++k) mid[d][k] = 0.0f;
             mn[d][0] = mn[d][1] = 0.0f;
-            if (M_out)
+            if (Lam_out)
 #pragma unroll
-                for (int k = 0; k < 29; ++k) M_out[(long)(d * 29 + k) * g.plane + pi] = 0.0;
+                for (int k = 0; k < LAM_STRIDE; ++k) Lam_out[(long)(d * LAM_STRIDE + k) * g.plane + pi] = 0.0f;
             continue;
         }
         const long pj = pix_of(g, nu, nv);
@@ -171,15 +174,11 @@ __device__ inline void complete_partials(const Geo& g, const Strengths& s, const
             ne = (double)sn[0] - (double)nl * rn;
         }
         accumulate_message(L, eta, e6, part + 6, ne, nl, mid[d], mn[d]);
-        if (M_out) {
-            // the new message in the per-factor layout (k_pf_messages)
-            double* o = M_out + (long)(d * 29) * g.plane + pi;
+        if (Lam_out) {
+            float* o = Lam_out + (long)(d * LAM_STRIDE) * g.plane + pi;
 #pragma unroll
-            for (int a = 0; a < 6; ++a) o[a * g.plane] = e6[a];
-#pragma unroll
-            for (int k = 0; k < 21; ++k) o[(6 + k) * g.plane] = (double)part[6 + k];
-            o[27 * g.plane] = ne;
-            o[28 * g.plane] = (double)nl;
+            for (int k = 0; k < 21; ++k) o[k * g.plane] = part[6 + k];
+            o[21 * g.plane] = nl;
         }
     }
 }
@@ -457,7 +456,7 @@ __device__ __attribute__((always_inline)) inline void prologue_pixel(const Geo& 
 template <bool FINAL>
 __device__ __attribute__((always_inline)) inline void iterate_pixel(const Geo& g, const Strengths& s, const Inputs& in, const float* __restrict__ X,
                                      float* __restrict__ Y, float* __restrict__ var_ll, float* __restrict__ valid,
-                                     int* __restrict__ health, int u, int v, double* __restrict__ M_out = nullptr,
+                                     int* __restrict__ health, int u, int v, float* __restrict__ Lam_out = nullptr,
                                      double* __restrict__ bel_out = nullptr) {
     const long p = pix_of(g, u, v);
     double tau[6], ell, R[9], t[3], L[28], eta[7];
@@ -465,7 +464,7 @@ __device__ __attribute__((always_inline)) inline void iterate_pixel(const Geo& g
     se3_exp(tau, R, t);
     const bool val = unary_factors(g, s, in, u, v, tau, R, t, ell, L, eta);
     float mid[4][27], mn[4][2];
-    complete_partials(g, s, in, X, u, v, R, t, ell, L, eta, mid, mn, M_out);
+    complete_partials(g, s, in, X, u, v, R, t, ell, L, eta, mid, mn, Lam_out);
     if (bel_out) {
         // the belief of the update (unary + new messages): L 28, eta 7
 #pragma unroll
@@ -516,51 +515,106 @@ __device__ inline bool normal_residual_c(float c, int d, double ell_i, double el
     return true;
 }
 
-template <bool FINAL>
+// Linearisation points of the neighbours: either loaded from the state and
+// exponentiated by every pixel that needs them (SH = false), or, in the
+// 64 x 4 workgroups of the single-sequence pass (SH = true), exponentiated
+// once per point into a shared table of the workgroup's points and its
+// one-pixel halo (HALO_W x HALO_H points, FP64 R, t and ell per point,
+// structure of arrays): each point's Exp is then computed by one lane instead
+// of five, and the neighbours' points are not loaded per pixel.
+constexpr int HALO_W = 66, HALO_H = 6, HALO_N = HALO_W * HALO_H;
+constexpr int SH_FIELDS = 13;   // R 9, t 3, ell
+
+__device__ inline void sh_put(double* __restrict__ sh, int h, const double R[9], const double t[3], double ell) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) sh[k * HALO_N + h] = R[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) sh[(9 + k) * HALO_N + h] = t[k];
+    sh[12 * HALO_N + h] = ell;
+}
+
+// the halo ring of a 64 x 4 tile at (u0, v0), lane l < 140: its point, or
+// false outside the image
+__device__ inline bool halo_point(const Geo& g, int u0, int v0, int l, int& u, int& v, int& h) {
+    int hx, hy;
+    if (l < HALO_W) { hx = l - 1; hy = -1; }
+    else if (l < 2 * HALO_W) { hx = l - HALO_W - 1; hy = 4; }
+    else if (l < 2 * HALO_W + 4) { hx = -1; hy = l - 2 * HALO_W; }
+    else { hx = 64; hy = l - 2 * HALO_W - 4; }
+    u = u0 + hx;
+    v = v0 + hy;
+    h = (hy + 1) * HALO_W + (hx + 1);
+    return u >= 0 && u < g.W && v >= 0 && v < g.H;
+}
+
+template <bool FINAL, bool SH>
 __device__ __attribute__((always_inline)) inline void iterate_pixel_pf(
     const Geo& g, const Strengths& s, const Inputs& in, const float* __restrict__ X, float* __restrict__ Y,
-    float* __restrict__ var_ll, float* __restrict__ valid, int* __restrict__ health, int u, int v) {
-    const long p = pix_of(g, u, v);
+    float* __restrict__ var_ll, float* __restrict__ valid, int* __restrict__ health, int u, int v,
+    bool inside = true, double* __restrict__ sh = nullptr, int u0 = 0, int v0 = 0, int tid = 0) {
+    const long p = inside ? pix_of(g, u, v) : 0;
     bool has[4];
     long pn[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
         int nu, nv;
-        has[d] = neighbour(g, u, v, d, nu, nv);
+        has[d] = inside && neighbour(g, u, v, d, nu, nv);
         pn[d] = has[d] ? pix_of(g, nu, nv) : p;
     }
     // --- loads with computable addresses, all issued before any use
-    float pt[7], npt[4][7];
-#pragma unroll
-    for (int k = 0; k < 7; ++k) pt[k] = X[(long)(P_TAU + k) * g.plane + p];
-#pragma unroll
-    for (int d = 0; d < 4; ++d)
-#pragma unroll
-        for (int k = 0; k < 7; ++k) npt[d][k] = X[(long)(P_TAU + k) * g.plane + pn[d]];
-    float mid[4][27], mn[4][2];
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-#pragma unroll
-        for (int k = 0; k < 27; ++k) mid[d][k] = X[(long)(P_MID + d * MID_STRIDE + k) * g.plane + p];
-        mn[d][0] = X[(long)(P_MN + 2 * d) * g.plane + p];
-        mn[d][1] = X[(long)(P_MN + 2 * d + 1) * g.plane + p];
-    }
+    float pt[7], npt[4][7], mid[4][27], mn[4][2];
     EdgeTargets ct;
-    ct.c[DIR_L] = in.cxt[pn[DIR_L]];
-    ct.c[DIR_R] = in.cxt[p];
-    ct.c[DIR_U] = in.cyt[pn[DIR_U]];
-    ct.c[DIR_D] = in.cyt[p];
-    const PixelInputs pin = load_pixel_inputs(g, s, in, u, v);
+    PixelInputs pin;
+    double tau[6], ell, R[9], t[3];
+    if (inside) {
+#pragma unroll
+        for (int k = 0; k < 7; ++k) pt[k] = X[(long)(P_TAU + k) * g.plane + p];
+        if constexpr (!SH) {
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+#pragma unroll
+                for (int k = 0; k < 7; ++k) npt[d][k] = X[(long)(P_TAU + k) * g.plane + pn[d]];
+        }
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+#pragma unroll
+            for (int k = 0; k < 27; ++k) mid[d][k] = X[(long)(P_MID + d * MID_STRIDE + k) * g.plane + p];
+            mn[d][0] = X[(long)(P_MN + 2 * d) * g.plane + p];
+            mn[d][1] = X[(long)(P_MN + 2 * d + 1) * g.plane + p];
+        }
+        ct.c[DIR_L] = in.cxt[pn[DIR_L]];
+        ct.c[DIR_R] = in.cxt[p];
+        ct.c[DIR_U] = in.cyt[pn[DIR_U]];
+        ct.c[DIR_D] = in.cyt[p];
+        pin = load_pixel_inputs(g, s, in, u, v);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) tau[k] = (double)pt[k];
+        ell = (double)pt[6];
+        se3_exp(tau, R, t);
+    }
+    if constexpr (SH) {
+        // the tile's points and its halo into the shared table
+        if (inside) sh_put(sh, (v - v0 + 1) * HALO_W + (u - u0 + 1), R, t, ell);
+        int hu, hv, hh;
+        if (tid < 2 * HALO_W + 8 && halo_point(g, u0, v0, tid, hu, hv, hh)) {
+            const long hp = pix_of(g, hu, hv);
+            double ht[6], hR[9], htr[3];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) ht[k] = (double)X[(long)(P_TAU + k) * g.plane + hp];
+            const double hell = (double)X[(long)P_ELL * g.plane + hp];
+            se3_exp(ht, hR, htr);
+            sh_put(sh, hh, hR, htr, hell);
+        }
+        __syncthreads();
+    }
+    if (!inside) return;
 
     // --- linearise at the current point
-    double tau[6], ell, R[9], t[3], L[28], eta[7];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) tau[k] = (double)pt[k];
-    ell = (double)pt[6];
-    se3_exp(tau, R, t);
+    double L[28], eta[7];
     const bool val = unary_factors(g, s, in, u, v, tau, R, t, ell, pin, L, eta);
 
     // --- complete the partials in flight (complete_partials)
+    const int hown = SH ? (v - v0 + 1) * HALO_W + (u - u0 + 1) : 0;
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
         if (!has[d]) {
@@ -569,11 +623,21 @@ __device__ __attribute__((always_inline)) inline void iterate_pixel_pf(
             mn[d][0] = mn[d][1] = 0.0f;
             continue;
         }
-        double tj[6], Rj[9], trj[3], r[6];
+        double Rj[9], trj[3], ellj, r[6];
+        if constexpr (SH) {
+            const int hj = hown + (d == DIR_L ? -1 : d == DIR_R ? 1 : d == DIR_U ? -HALO_W : HALO_W);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) tj[k] = (double)npt[d][k];
-        const double ellj = (double)npt[d][6];
-        se3_exp(tj, Rj, trj);
+            for (int k = 0; k < 9; ++k) Rj[k] = sh[k * HALO_N + hj];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) trj[k] = sh[(9 + k) * HALO_N + hj];
+            ellj = sh[12 * HALO_N + hj];
+        } else {
+            double tj[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) tj[k] = (double)npt[d][k];
+            ellj = (double)npt[d][6];
+            se3_exp(tj, Rj, trj);
+        }
         se3_between(Rj, trj, R, t, r);
         double e6[6];
 #pragma unroll
@@ -652,14 +716,17 @@ __global__ __launch_bounds__(256) void k_fu_prologue(Geo g, Strengths s, Inputs 
     prologue_pixel(g, s, in, X, Y, health, u, v);
 }
 
+// one 64 x 4 tile per workgroup; every lane reaches the barrier of the shared
+// table, lanes outside the image only help fill it
 template <bool FINAL>
 __global__ __launch_bounds__(256) void k_fu_iterate(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
                                                     float* __restrict__ Y, float* __restrict__ var_ll,
                                                     float* __restrict__ valid, int* __restrict__ health) {
-    const int u = blockIdx.x * blockDim.x + threadIdx.x;
-    const int v = blockIdx.y * blockDim.y + threadIdx.y;
-    if (u >= g.W || v >= g.H) return;
-    iterate_pixel_pf<FINAL>(g, s, in, X, Y, var_ll, valid, health, u, v);
+    __shared__ double sh[SH_FIELDS * HALO_N];
+    const int u0 = blockIdx.x * 64, v0 = blockIdx.y * 4;
+    const int u = u0 + threadIdx.x, v = v0 + threadIdx.y;
+    iterate_pixel_pf<FINAL, true>(g, s, in, X, Y, var_ll, valid, health, u, v, u < g.W && v < g.H, sh, u0, v0,
+                                  threadIdx.y * 64 + threadIdx.x);
 }
 
 // the same passes for the reverse sweep's recompute: the prologue also writes
@@ -676,7 +743,7 @@ __global__ __launch_bounds__(256) void k_fu_prologue_tape(Geo g, Strengths s, In
 }
 
 __global__ __launch_bounds__(256) void k_fu_final_tape(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
-                                                       float* __restrict__ Y, double* __restrict__ M,
+                                                       float* __restrict__ Y, float* __restrict__ M,
                                                        double* __restrict__ bel, float* __restrict__ var_ll,
                                                        float* __restrict__ valid, int* __restrict__ health) {
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
@@ -819,7 +886,7 @@ __global__ __launch_bounds__(256) void k_batch_iterate(const SeqDesc* __restrict
     if (!batch_pixel(seqs, work, d, u, v, item)) return;
     const float* X = parity ? d->X1 : d->X0;
     float* Y = parity ? d->X0 : d->X1;
-    iterate_pixel_pf<FINAL>(d->g, s, d->in, X, Y, d->var_ll, d->valid, health, u, v);
+    iterate_pixel_pf<FINAL, false>(d->g, s, d->in, X, Y, d->var_ll, d->valid, health, u, v);
 }
 
 // per work item: sum of the six pose planes, valid count, non-finite count of
@@ -951,7 +1018,7 @@ __global__ __launch_bounds__(256) void k_batch_persistent(const SeqDesc* __restr
             if (u < d->g.W && v < d->g.H) {
                 const float* X = par ? d->X1 : d->X0;
                 float* Y = par ? d->X0 : d->X1;
-                iterate_pixel_pf<false>(d->g, s, d->in, X, Y, d->var_ll, d->valid, health, u, v);
+                iterate_pixel_pf<false, false>(d->g, s, d->in, X, Y, d->var_ll, d->valid, health, u, v);
             }
         }
         if (pass + 1 < n_passes) grid.sync();
@@ -1099,7 +1166,7 @@ hipError_t launch_fu_iterate(const Geo& g, const Strengths& s, const Inputs& in,
 }
 
 hipError_t launch_fu_step_tape(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* tmp,
-                               float* Y, double* marg, double* M, double* bel, float* var_ll, float* valid,
+                               float* Y, double* marg, float* M, double* bel, float* var_ll, float* valid,
                                int* health, hipStream_t st) {
     hipLaunchKernelGGL(k_fu_prologue_tape, grid2d(g, kBlockFused), kBlockFused, 0, st, g, s, in, X, tmp, marg, health);
     hipLaunchKernelGGL(k_fu_final_tape, grid2d(g, kBlockFused), kBlockFused, 0, st, g, s, in, tmp, Y, M, bel, var_ll, valid,

@@ -25,11 +25,13 @@
 using namespace pv;
 
 namespace {
-constexpr int MSG_PLANES = 116;  // 4 x (eta 6, Lambda 21, normal eta, normal lambda)
+constexpr int MSG_PLANES = 116;  // 4 x (eta 6, Lambda 21, normal eta, normal lambda): cotangents (FP64)
+constexpr int LAM_PLANES = 88;   // 4 x (Lambda 21, normal lambda): the tape of new messages (FP32)
 constexpr int MARG_PLANES = 64;  // pose marginal 21 + 6, depth marginal 2, their belief 28 + 7
 constexpr int BEL_PLANES = 35;   // belief of the update: 28 + 7
 constexpr int UB_PLANES = 42;
 constexpr int EB_PLANES = 36;
+constexpr int CB_PLANES = 29;
 }  // namespace
 
 struct pixvod_unroll {
@@ -44,16 +46,19 @@ struct pixvod_unroll {
     float *frames = nullptr, *stage = nullptr;
     float *X0 = nullptr, *Xw[2] = {nullptr, nullptr}, *tape = nullptr, *Xend = nullptr, *seg = nullptr;
     float *var_ll = nullptr, *valid = nullptr;
-    double *marg = nullptr, *M = nullptr, *bel = nullptr, *Mb = nullptr, *Ub = nullptr, *Eb = nullptr;
+    double *marg = nullptr, *bel = nullptr, *Mb = nullptr, *Ub = nullptr, *Eb = nullptr;
+    float* M = nullptr;
     // the reverse sweep recomputes the next segment on a side stream while
     // the current one is reversed: a second set of recompute buffers (and of
     // frame-prep planes, for segments of the next frame)
     float *seg2 = nullptr, *tmp2 = nullptr, *sink2 = nullptr, *It2 = nullptr, *Gx2 = nullptr, *Gy2 = nullptr;
-    double *marg2 = nullptr, *M2 = nullptr, *bel2 = nullptr;
+    double *marg2 = nullptr, *bel2 = nullptr;
+    float* M2 = nullptr;
     hipStream_t side = nullptr;
     std::vector<hipEvent_t> evs;      // two per segment of a reverse sweep
 
     float* Xb[2] = {nullptr, nullptr};
+    float* Cb[2] = {nullptr, nullptr};   // slot-common message cotangents (with Xb)
     double *gsig = nullptr, *gN = nullptr, *gk = nullptr;
     double *partial = nullptr, *stats = nullptr, *h_stats = nullptr;
     int* health = nullptr;
@@ -130,7 +135,7 @@ static bool ualloc(T** p, size_t n) {
 static void urelease(pixvod_unroll* u) {
     void* bufs[] = {u->Is, u->cxt, u->cyt, u->sig, u->It, u->Gx, u->Gy, u->frames, u->stage, u->X0, u->Xw[0],
                     u->Xw[1], u->tape, u->Xend, u->seg, u->var_ll, u->valid, u->marg, u->M, u->bel, u->Mb, u->Ub, u->Eb,
-                    u->seg2, u->tmp2, u->sink2, u->It2, u->Gx2, u->Gy2, u->marg2, u->M2, u->bel2,
+                    u->Cb[0], u->Cb[1], u->seg2, u->tmp2, u->sink2, u->It2, u->Gx2, u->Gy2, u->marg2, u->M2, u->bel2,
                     u->Xb[0], u->Xb[1], u->gsig, u->gN, u->gk, u->partial, u->stats, u->health};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -214,15 +219,16 @@ int pixvod_unroll_create(int H, int W, const pixvod_intrinsics* K, const pixvod_
               ualloc(&u->Xw[0], S) && ualloc(&u->Xw[1], S) && ualloc(&u->tape, S * (size_t)max_frames * spf) &&
               ualloc(&u->Xend, S) && ualloc(&u->seg, S * (size_t)ckpt_every) && ualloc(&u->var_ll, pl) &&
               ualloc(&u->valid, pl) && ualloc(&u->marg, pl * MARG_PLANES * (size_t)ckpt_every) &&
-              ualloc(&u->M, pl * MSG_PLANES * (size_t)ckpt_every) &&
+              ualloc(&u->M, pl * LAM_PLANES * (size_t)ckpt_every) &&
               ualloc(&u->bel, pl * BEL_PLANES * (size_t)ckpt_every) &&
               ualloc(&u->Mb, pl * MSG_PLANES) && ualloc(&u->Ub, pl * UB_PLANES) && ualloc(&u->Eb, pl * EB_PLANES) &&
               ualloc(&u->Xb[0], S) && ualloc(&u->Xb[1], S) && ualloc(&u->gsig, pl) && ualloc(&u->gN, pl) &&
               ualloc(&u->gk, pl) && ualloc(&u->partial, (size_t)nb * 8) &&
+              ualloc(&u->Cb[0], pl * CB_PLANES) && ualloc(&u->Cb[1], pl * CB_PLANES) &&
               ualloc(&u->seg2, S * (size_t)ckpt_every) && ualloc(&u->tmp2, S) && ualloc(&u->sink2, S) &&
               ualloc(&u->It2, pl) && ualloc(&u->Gx2, pl) && ualloc(&u->Gy2, pl) &&
               ualloc(&u->marg2, pl * MARG_PLANES * (size_t)ckpt_every) &&
-              ualloc(&u->M2, pl * MSG_PLANES * (size_t)ckpt_every) &&
+              ualloc(&u->M2, pl * LAM_PLANES * (size_t)ckpt_every) &&
               ualloc(&u->bel2, pl * BEL_PLANES * (size_t)ckpt_every) &&
               ualloc(&u->stats, (size_t)max_frames * 8 + 8) && ualloc(&u->health, 1);
     if (ok) ok = hipHostMalloc((void**)&u->h_stats, ((size_t)max_frames * 8 + 8) * sizeof(double)) == hipSuccess;
@@ -379,6 +385,8 @@ int pixvod_unroll_backward(pixvod_unroll* u, const double* xi_bar, const float* 
     UHIP(hipEventRecord(u->ev[2], u->stream));
     UHIP(hipMemsetAsync(u->Xb[0], 0, S * sizeof(float), u->stream));
     UHIP(hipMemsetAsync(u->Xb[1], 0, S * sizeof(float), u->stream));
+    UHIP(hipMemsetAsync(u->Cb[0], 0, pl * CB_PLANES * sizeof(float), u->stream));
+    UHIP(hipMemsetAsync(u->Cb[1], 0, pl * CB_PLANES * sizeof(float), u->stream));
     UHIP(hipMemsetAsync(u->gsig, 0, pl * sizeof(double), u->stream));
     UHIP(hipMemsetAsync(u->gN, 0, pl * sizeof(double), u->stream));
     UHIP(hipMemsetAsync(u->gk, 0, pl * sizeof(double), u->stream));
@@ -391,7 +399,9 @@ int pixvod_unroll_backward(pixvod_unroll* u, const double* xi_bar, const float* 
     const int S_ = u->seg_per_frame, T = F * S_;
     struct Set {
         float *seg, *tmp, *sink;
-        double *marg, *M, *bel;
+        double* marg;
+        float* M;
+        double* bel;
     };
     const Set sets[2] = {{u->seg, u->Xw[0], u->Xw[1], u->marg, u->M, u->bel},
                          {u->seg2, u->tmp2, u->sink2, u->marg2, u->M2, u->bel2}};
@@ -430,7 +440,7 @@ int pixvod_unroll_backward(pixvod_unroll* u, const double* xi_bar, const float* 
         for (int k = 0; k < len; ++k) {
             float* dst = (k + 1 < len) ? B.seg + S * (k + 1) : B.sink;
             UHIP(launch_fu_step_tape(g, s, I, B.seg + S * k, B.tmp, dst, B.marg + pl * MARG_PLANES * k,
-                                     B.M + pl * MSG_PLANES * k, B.bel + pl * BEL_PLANES * k, u->var_ll, u->valid,
+                                     B.M + pl * LAM_PLANES * k, B.bel + pl * BEL_PLANES * k, u->var_ll, u->valid,
                                      u->health, u->side));
         }
         UHIP(hipEventRecord(evC[i], u->side));
@@ -467,11 +477,12 @@ int pixvod_unroll_backward(pixvod_unroll* u, const double* xi_bar, const float* 
         for (int k = seg_len(u, sg) - 1; k >= 0; --k) {
             const float* X = B.seg + S * k;
             const double* marg = B.marg + pl * MARG_PLANES * k;
-            const double* M = B.M + pl * MSG_PLANES * k;
+            const float* M = B.M + pl * LAM_PLANES * k;
             const double* bel = B.bel + pl * BEL_PLANES * k;
-            UHIP(launch_adj_update(g, s, I, X, M, bel, u->Xb[cur], u->Mb, u->Ub, u->stream));
+            UHIP(launch_adj_update(g, s, I, X, M, bel, u->Xb[cur], u->Cb[cur], u->Mb, u->Ub, u->stream));
             UHIP(launch_adj_edges(g, s, I, X, marg, M, u->Mb, u->Xb[cur ^ 1], u->Eb, u->gN, u->stream));
-            UHIP(launch_adj_belief(g, s, I, X, marg, u->Ub, u->Eb, u->Xb[cur ^ 1], u->gsig, u->gk, u->stream));
+            UHIP(launch_adj_belief(g, s, I, X, marg, u->Ub, u->Eb, u->Xb[cur ^ 1], u->Cb[cur ^ 1], u->gsig, u->gk,
+                                   u->stream));
             cur ^= 1;
         }
         UHIP(hipEventRecord(evR[i], u->stream));

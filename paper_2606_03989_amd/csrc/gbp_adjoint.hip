@@ -165,7 +165,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_update(Geo g, Strengths s, Input
 // pixel are adjacent; their contributions to j's marginal and perturbation
 // cotangents are summed with lane shuffles and written by the d = 0 lane.
 // Writes the sender part of j's slot-d cotangent to Xbo.
-__global__ __launch_bounds__(256) void k_adj_edges(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
+__global__ __launch_bounds__(256, 2) void k_adj_edges(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
                                                    const double* __restrict__ marg, const float* __restrict__ M,
                                                    const double* __restrict__ Mb, float* __restrict__ Xbo,
                                                    double* __restrict__ Eb, double* __restrict__ gN) {

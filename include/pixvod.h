@@ -404,7 +404,7 @@ int pixvod_unroll_last_ms(const pixvod_unroll* u, double* forward_ms, double* ba
  * diagonal) until the residual norm falls below cg_tol times its initial
  * value or max_cg iterations, then sets xi <- Log(Exp(xi) Exp(d_xi)),
  * ell <- ell + d_ell. Parameters as pixvod_params (sigma_R unused; a constant
- * sigma_D). Device memory: 15 FP64 and 6 FP32 planes of H x W.
+ * sigma_D). Device memory: 17 FP64 and 6 FP32 planes of H x W.
  */
 typedef struct pixvod_central pixvod_central;
 
@@ -431,7 +431,9 @@ int pixvod_central_set_point(pixvod_central* c, const double xi[6], const double
 int pixvod_central_get_point(pixvod_central* c, double xi[6], double* log_depth);
 /* n_iters >= 0 IRLS iterations on `frame` (H*W) from the current point
  * (warm start); xi_out (host, may be NULL), inv_depth (H*W at out_where, may
- * be NULL), stats (may be NULL). ESTATE before a keyframe. */
+ * be NULL), stats (may be NULL). ESTATE before a keyframe. Synchronous: the
+ * host reads the CG stop test between chunks of 16 CG iterations on the
+ * solver's stream. */
 int pixvod_central_track(pixvod_central* c, const float* frame, int where, int n_iters, double xi_out[6],
                          float* inv_depth, int out_where, pixvod_central_stats* stats);
 /* duration (ms, HIP events) of the last call's IRLS iterations */

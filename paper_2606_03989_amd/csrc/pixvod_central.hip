@@ -18,11 +18,24 @@
 //        [B' D ] [d_ell] = [g_ell],  D = diag + lamN * graph Laplacian,
 //      by preconditioned conjugate gradients with a block-Jacobi
 //      preconditioner (A^-1 for the pose, 1/D_ii for the depths), FP64
-//      vectors, to a relative residual tolerance; a device flag ends the
-//      remaining launches once it is met;
+//      vectors, to a relative residual tolerance;
 //   3. applies xi <- Log(Exp(xi) Exp(d_xi)), ell <- ell + d_ell.
-// Each CG iteration is four launches: the stencil product and its reductions,
-// the pose-block scalar step, the vector update, the next direction's scalars.
+// The conjugate gradients take the single-reduction form of Chronopoulos and
+// Gear (1989): with u = P^-1 r and w = M u carried along, the two inner
+// products of an iteration (r.u, w.u) come out of one reduction, so each CG
+// iteration is one launch over the pixels. The launch updates p, s = M p, x
+// and r, forms the new u and, from the neighbours' new u (recomputed by each
+// pixel from the neighbours' stored r, w, s, so that no pixel waits for
+// another), the new w, and writes per-workgroup partial sums. Its scalar step
+// (alpha and beta from the previous launch's partial sums, the pose block's
+// part of every vector, the stop test) is evaluated by every workgroup in
+// one fixed order, so all take the same values. The scalars pass between
+// launches in two alternating records, the per-pixel vectors read by
+// neighbours (r, w, s) in two alternating plane sets, the partial sums in two
+// alternating buffers, so no launch reads what it writes. The host launches
+// the iterations in chunks and stops after the chunk that follows the first
+// one whose end state reports convergence (launches after convergence return
+// at once).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,73 +54,106 @@ using namespace pv;
 namespace {
 
 constexpr int kThreads = 256;      // 64 x 4 pixel blocks
-constexpr int kLinPartials = 30;   // A (21), g_xi (6), r.z, r.r, valid count
-constexpr int kMvPartials = 7;     // sum b_i p_i (6), p.q
-constexpr int kUpPartials = 2;     // r.z, r.r
+constexpr int kLinPartials = 29;   // A (21), g_xi (6), r.r, valid count
+constexpr int kCgPartials = 9;     // r.u, w.u, r.r, sum b_i u_i (6)
+constexpr int kCgThreads = 256;    // work-items per workgroup of the CG launches
+constexpr int kCgPx = 2;           // pixels per work-item and round in those launches
+constexpr int kCgMaxBlocks = 1024; // most workgroups of those launches (a multiple of 8)
+constexpr int kCgChunk = 16;       // CG iterations launched between convergence checks
 
 // solver state in device memory
 struct CgState {
     double xi[6];
     double A[21];        // pose block, packed upper
+    double Ainv[21];     // its inverse (the pose part of the preconditioner)
     double g[6];         // pose right-hand side
-    double x[6], r[6], z[6], p[6];
-    double rz, alpha, beta, rr0, rr;
+    double x[6];         // the pose step of the last solve
+    double rr0, rr;      // |r|^2 at the start and the end of the last solve
     double nvalid;
     int done, iters;     // this solve
     int total;           // CG iterations since the frame started
 };
 
+// the CG state between launches: pose parts of the vectors and the scalars
+// of the last step
+struct CgIter {
+    double x[6], r[6], u[6], p[6], s[6];
+    double gamma, alpha, rr;
+    int done, iters;
+};
+
 struct Planes {            // per-pixel FP64 planes (pitched)
-    double *ell, *diag, *b, *gl, *x, *r, *z, *p0, *p1, *q;
+    double *ell, *diag, *b, *gl, *x, *p;
+    double *r[2], *w[2], *s[2];   // read by neighbours: two alternating sets
 };
 
 // ---------------------------------------------------------------------------
-// block reduction of `n` doubles per thread into partial[block * n + k]
+// reductions: wavefront butterflies of lane exchanges, then the wavefronts'
+// sums in order. Every step adds the same two operands in every lane (in
+// either order), so all lanes hold the same sum, and a reduction evaluated
+// in several workgroups over the same data gives the same value in each.
 
 template <int NV>
+__device__ inline void wave_sum(double v[NV]) {
+    for (int m = 32; m > 0; m >>= 1)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], m, 64);
+}
+
+// workgroup (NT work-items) sum of NV doubles per work-item into
+// partial[block * NV + k]
+template <int NV, int NT>
 __device__ inline void block_reduce(double v[NV], double* __restrict__ partial) {
-    __shared__ double sh[kThreads];
+    __shared__ double sh[NT / 64][NV];
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
-    const int nthreads = blockDim.x * blockDim.y;
+    const int lane = tid & 63, w = tid >> 6;
     const long blk = (long)blockIdx.x + (long)blockIdx.y * gridDim.x;
-    for (int k = 0; k < NV; ++k) {
-        sh[tid] = v[k];
-        __syncthreads();
-        for (int s = nthreads / 2; s > 0; s >>= 1) {
-            if (tid < s) sh[tid] += sh[tid + s];
-            __syncthreads();
-        }
-        if (tid == 0) partial[blk * NV + k] = sh[0];
-        __syncthreads();
+    wave_sum<NV>(v);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sh[w][k] = v[k];
+    __syncthreads();
+    if (tid < NV) {
+        double t = 0.0;
+        for (int j = 0; j < NT / 64; ++j) t += sh[j][tid];
+        partial[blk * NV + tid] = t;
     }
 }
 
-// single-workgroup sum of nb partial records of NV doubles, fixed order
-template <int NV>
+// sum of nb partial records of NV doubles, in one fixed order, given to
+// every work-item of the workgroup (NT work-items, 1-D); once per kernel
+template <int NV, int NT>
 __device__ inline void final_sum(const double* __restrict__ partial, int nb, double out[NV]) {
-    __shared__ double sh[kThreads];
-    const int tid = threadIdx.x;
-    for (int k = 0; k < NV; ++k) {
-        double s = 0.0;
-        for (int b = tid; b < nb; b += kThreads) s += partial[(long)b * NV + k];
-        sh[tid] = s;
-        __syncthreads();
-        for (int st = kThreads / 2; st > 0; st >>= 1) {
-            if (tid < st) sh[tid] += sh[tid + st];
-            __syncthreads();
-        }
-        out[k] = sh[0];
-        __syncthreads();
+    __shared__ double sh[NT / 64][NV];
+    __shared__ double tot[NV];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double t[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) t[k] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += NT)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) t[k] += partial[(long)b * NV + k];
+    wave_sum<NV>(t);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sh[w][k] = t[k];
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double u = 0.0;
+        for (int j = 0; j < NT / 64; ++j) u += sh[j][threadIdx.x];
+        tot[threadIdx.x] = u;
     }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) out[k] = tot[k];
 }
 
-// z = A^-1 r for the packed 6x6 pose block
-__device__ inline void pose_precondition(const double A[21], const double r[6], double z[6]) {
+// inverse of the packed 6x6 pose block (through its Cholesky factor)
+__device__ inline void pose_inverse(const double A[21], double Ai[21]) {
     double L[21], idg[6];
     for (int k = 0; k < 21; ++k) L[k] = A[k];
     chol6(L, idg);
-    for (int k = 0; k < 6; ++k) z[k] = r[k];
-    chol6_solve(L, idg, z);
+    chol6_inverse(L, idg, Ai);
 }
 
 __device__ inline double dot6(const double a[6], const double b[6]) {
@@ -187,7 +233,22 @@ __global__ void k_c_keyframe(Geo g, const float* __restrict__ img, const float* 
     cyt[p] = ok ? (float)(n1 / (g.fy * nq)) : __int_as_float(0x7fc00000);
 }
 
-// linearisation at the shared pose and CG start (x = 0, r = g, z = P^-1 r, p = z)
+// per pixel, bit d: the normal edge to neighbour d exists and is active (a
+// keyframe property)
+__global__ void k_c_edges(Geo g, Inputs in, unsigned char* __restrict__ act) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y * blockDim.y + threadIdx.y;
+    if (u >= g.W || v >= g.H) return;
+    const long pi = pix_of(g, u, v);
+    int a = 0;
+    for (int d = 0; d < 4; ++d) {
+        int nu, nv;
+        if (neighbour(g, u, v, d, nu, nv) && normal_active(g, in, pi, pix_of(g, nu, nv), d)) a |= 1 << d;
+    }
+    act[pi] = (unsigned char)a;
+}
+
+// linearisation at the shared pose and CG start (x = 0, r = g)
 __global__ __launch_bounds__(kThreads) void k_c_linearise(Geo g, Strengths s, Inputs in,
                                                           const CgState* __restrict__ cs, Planes P,
                                                           double* __restrict__ partial) {
@@ -222,135 +283,307 @@ __global__ __launch_bounds__(kThreads) void k_c_linearise(Geo g, Strengths s, In
         P.diag[pi] = diag;
         for (int k = 0; k < 6; ++k) P.b[(long)k * g.plane + pi] = L[s7(k, 6)];
         P.gl[pi] = gl;
-        const double z = gl / diag;
         P.x[pi] = 0.0;
-        P.r[pi] = gl;
-        P.z[pi] = z;
-        P.p0[pi] = z;
+        P.r[0][pi] = gl;
         for (int r = 0, k = 0; r < 6; ++r)
             for (int c = r; c < 6; ++c) red[k++] = L[s7(r, c)];
         for (int k = 0; k < 6; ++k) red[21 + k] = eta[k];
-        red[27] = gl * z;
-        red[28] = gl * gl;
-        red[29] = val ? 1.0 : 0.0;
+        red[27] = gl * gl;
+        red[28] = val ? 1.0 : 0.0;
     }
-    block_reduce<kLinPartials>(red, partial);
+    block_reduce<kLinPartials, kThreads>(red, partial);
 }
 
+// the pose block, its inverse, the pose part of the CG start (x = 0, r = g,
+// u = A^-1 g) and |r_0|^2
 __global__ __launch_bounds__(kThreads) void k_c_lin_final(Strengths s, int nb, const double* __restrict__ partial,
-                                                          CgState* __restrict__ cs) {
+                                                          CgState* __restrict__ cs, CgIter* __restrict__ rec0) {
     double tot[kLinPartials];
-    final_sum<kLinPartials>(partial, nb, tot);
+    final_sum<kLinPartials, kThreads>(partial, nb, tot);
     if (threadIdx.x != 0) return;
     double xi[6];
     for (int k = 0; k < 6; ++k) xi[k] = cs->xi[k];
     add_pose_prior(s, xi, tot, tot + 21);
     for (int k = 0; k < 21; ++k) cs->A[k] = tot[k];
+    for (int k = 0; k < 6; ++k) cs->g[k] = tot[21 + k];
+    pose_inverse(cs->A, cs->Ainv);
+    CgIter st;
     for (int k = 0; k < 6; ++k) {
-        cs->g[k] = tot[21 + k];
-        cs->x[k] = 0.0;
-        cs->r[k] = tot[21 + k];
+        st.x[k] = 0.0;
+        st.r[k] = cs->g[k];
+        st.p[k] = 0.0;
+        st.s[k] = 0.0;
     }
-    pose_precondition(cs->A, cs->r, cs->z);
-    for (int k = 0; k < 6; ++k) cs->p[k] = cs->z[k];
-    cs->rz = tot[27] + dot6(cs->r, cs->z);
-    cs->rr0 = tot[28] + dot6(cs->r, cs->r);
+    sym6_mul(cs->Ainv, st.r, st.u);
+    cs->rr0 = tot[27] + dot6(st.r, st.r);
     cs->rr = cs->rr0;
-    cs->beta = 0.0;
-    cs->alpha = 0.0;
-    cs->nvalid = tot[29];
+    cs->nvalid = tot[28];
     cs->iters = 0;
     cs->done = (cs->rr0 > 0.0) ? 0 : 1;
+    st.gamma = 0.0;
+    st.alpha = 0.0;
+    st.rr = cs->rr0;
+    st.done = cs->done;
+    st.iters = 0;
+    *rec0 = st;
 }
 
-// q = M p with p = z + beta p_prev formed on the fly (written to p_out)
-__global__ __launch_bounds__(kThreads) void k_c_matvec(Geo g, Strengths s, Inputs in, const CgState* __restrict__ cs,
-                                                       Planes P, const double* __restrict__ p_in,
-                                                       double* __restrict__ p_out, double* __restrict__ partial) {
-    if (cs->done) return;
-    const int u = blockIdx.x * blockDim.x + threadIdx.x;
-    const int v = blockIdx.y * blockDim.y + threadIdx.y;
-    const double beta = cs->beta;
-    double red[kMvPartials];
-    for (int k = 0; k < kMvPartials; ++k) red[k] = 0.0;
-    if (u < g.W && v < g.H) {
-        const long pi = pix_of(g, u, v);
-        const double pv_ = P.z[pi] + beta * p_in[pi];
-        double q = P.diag[pi] * pv_;
-        if (s.lamN > 0.0) {
-            for (int d = 0; d < 4; ++d) {
-                int nu, nv;
-                if (!neighbour(g, u, v, d, nu, nv)) continue;
-                const long pj = pix_of(g, nu, nv);
-                if (normal_active(g, in, pi, pj, d)) q -= s.lamN * (P.z[pj] + beta * p_in[pj]);
-            }
-        }
-        for (int k = 0; k < 6; ++k) {
-            const double bk = P.b[(long)k * g.plane + pi];
-            q += bk * cs->p[k];
-            red[k] = bk * pv_;
-        }
-        p_out[pi] = pv_;
-        P.q[pi] = q;
-        red[6] = pv_ * q;
-    }
-    block_reduce<kMvPartials>(red, partial);
+// The CG launches: kCgThreads work-items per workgroup, kCgPx pixels per
+// work-item and round (range base + j * kCgThreads + work-item). Workgroup b
+// takes range (b mod 8) * (nbx / 8) + b / 8 (nbx, the grid, a multiple of 8):
+// workgroups are dealt to the eight XCDs in turn, so each XCD gets adjacent
+// ranges and finds most of their vertical neighbours in its own L2. Rounds
+// stride over the image when the grid is smaller than it. The first round's
+// own-pixel loads are issued before the scalar step, which does not depend on
+// them; the neighbours' (L1 and L2 hits: other work-items load them as their
+// own) after it.
+
+__device__ inline int cg_range(int b, int nbx) { return (b & 7) * (nbx >> 3) + (b >> 3); }
+
+struct CgPix {             // what an iteration needs of one pixel's own planes
+    int u, v, act;
+    double x, p, r, w, s, diag, b[6];
+};
+
+__device__ inline void cg_load(const Geo& g, const Planes& P, const unsigned char* __restrict__ act, int cur,
+                               bool first, int i, CgPix& a) {
+    a.u = i % g.W;
+    a.v = i / g.W;
+    const long pi = pix_of(g, a.u, a.v);
+    a.act = act[pi];
+    a.x = P.x[pi];
+    a.p = first ? 0.0 : P.p[pi];
+    a.r = P.r[cur][pi];
+    a.w = P.w[cur][pi];
+    a.s = first ? 0.0 : P.s[cur][pi];
+    a.diag = P.diag[pi];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a.b[k] = P.b[(long)k * g.plane + pi];
 }
 
-__global__ __launch_bounds__(kThreads) void k_c_alpha(int nb, const double* __restrict__ partial,
-                                                      CgState* __restrict__ cs) {
-    if (cs->done) return;
-    double tot[kMvPartials];
-    final_sum<kMvPartials>(partial, nb, tot);
-    if (threadIdx.x != 0) return;
-    double qx[6];
-    sym6_mul(cs->A, cs->p, qx);
-    for (int k = 0; k < 6; ++k) qx[k] += tot[k];
-    const double pq = tot[6] + dot6(cs->p, qx);
-    const double alpha = cs->rz / pq;
-    cs->alpha = alpha;
+// one pixel's new residual and preconditioned residual from its stored r, w,
+// s (explicit FMAs, so that a pixel and its neighbours evaluate the same
+// expression bit for bit)
+__device__ inline double cg_new_r(double r, double w, double s_prev, double alpha, double beta, bool first,
+                                  double& s_new) {
+    s_new = first ? w : fma(beta, s_prev, w);
+    return fma(-alpha, s_new, r);
+}
+
+// w = M u at one pixel: the diagonal, the active normal edges and the pose
+// column, with the partial sums of r.u, w.u, r.r and b_k u
+__device__ inline void cg_apply_pixel(double diag, const double b[6], const double un[4], int act, double lamN,
+                                      const double upose[6], double r, double u, double& w, double red[kCgPartials]) {
+    double q = diag * u;
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+        if (act & (1 << d)) q -= lamN * un[d];
+#pragma unroll
     for (int k = 0; k < 6; ++k) {
-        cs->x[k] += alpha * cs->p[k];
-        cs->r[k] -= alpha * qx[k];
+        q += b[k] * upose[k];
+        red[3 + k] += b[k] * u;
     }
-    pose_precondition(cs->A, cs->r, cs->z);
+    w = q;
+    red[0] += r * u;
+    red[1] += q * u;
+    red[2] += r * r;
 }
 
-__global__ __launch_bounds__(kThreads) void k_c_update(Geo g, const CgState* __restrict__ cs, Planes P,
-                                                       const double* __restrict__ p_cur, double* __restrict__ partial) {
-    if (cs->done) return;
-    const int u = blockIdx.x * blockDim.x + threadIdx.x;
-    const int v = blockIdx.y * blockDim.y + threadIdx.y;
-    double red[kUpPartials] = {0.0, 0.0};
-    if (u < g.W && v < g.H) {
-        const long pi = pix_of(g, u, v);
-        const double alpha = cs->alpha;
-        P.x[pi] += alpha * p_cur[pi];
-        const double r = P.r[pi] - alpha * P.q[pi];
-        P.r[pi] = r;
-        const double z = r / P.diag[pi];
-        P.z[pi] = z;
-        red[0] = r * z;
-        red[1] = r * r;
+// CG start: u_0 = P^-1 r_0 and w_0 = M u_0 (planes of set 0), partial sums
+__global__ __launch_bounds__(kCgThreads) void k_c_cg_init(Geo g, Strengths s, Planes P,
+                                                          const unsigned char* __restrict__ act,
+                                                          const CgIter* __restrict__ rec0,
+                                                          double* __restrict__ part_out) {
+    __shared__ double sh_u[6];
+    __shared__ int sh_done;
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 6; ++k) sh_u[k] = rec0->u[k];
+        sh_done = rec0->done;
     }
-    block_reduce<kUpPartials>(red, partial);
+    __syncthreads();
+    if (sh_done) return;
+    double up[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) up[k] = sh_u[k];
+    double red[kCgPartials];
+#pragma unroll
+    for (int k = 0; k < kCgPartials; ++k) red[k] = 0.0;
+    const int N = g.H * g.W;
+    const int round = kCgThreads * kCgPx;
+    for (int rb = cg_range(blockIdx.x, gridDim.x); rb * round < N; rb += gridDim.x) {
+#pragma unroll
+        for (int j = 0; j < kCgPx; ++j) {
+            const int i = rb * round + j * kCgThreads + threadIdx.x;
+            if (i >= N) continue;
+            const int u = i % g.W, v = i / g.W;
+            const long pi = pix_of(g, u, v);
+            const double r = P.r[0][pi], diag = P.diag[pi];
+            double b[6], un[4];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) b[k] = P.b[(long)k * g.plane + pi];
+            const int ea = s.lamN > 0.0 ? act[pi] : 0;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                un[d] = 0.0;
+                if (ea & (1 << d)) {
+                    int nu, nv;
+                    neighbour(g, u, v, d, nu, nv);
+                    const long pj = pix_of(g, nu, nv);
+                    un[d] = P.r[0][pj] / P.diag[pj];
+                }
+            }
+            double w;
+            cg_apply_pixel(diag, b, un, ea, s.lamN, up, r, r / diag, w, red);
+            P.w[0][pi] = w;
+        }
+    }
+    block_reduce<kCgPartials, kCgThreads>(red, part_out);
 }
 
-__global__ __launch_bounds__(kThreads) void k_c_beta(int nb, const double* __restrict__ partial,
-                                                     CgState* __restrict__ cs, double tol2) {
-    if (cs->done) return;
-    double tot[kUpPartials];
-    final_sum<kUpPartials>(partial, nb, tot);
+// CG iteration k (planes of set cur in, set 1 - cur out): the scalar step
+//   gamma = r.u, delta = w.u (w's pose part: A u + sum b_i u_i), stop test,
+//   beta = gamma / gamma_prev, alpha = gamma / (delta - beta gamma / alpha_prev)
+//   (k = 0: beta = 0, alpha = gamma / delta),
+// then p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s, u = P^-1 r,
+// w = M u and the partial sums for the next step. The scalar step runs on the
+// first work-item of each workgroup and reaches the others via LDS.
+__global__ __launch_bounds__(kCgThreads, 3) void k_c_cg_iter(Geo g, Strengths s, const CgState* __restrict__ cs,
+                                                             Planes P, const unsigned char* __restrict__ act,
+                                                             const CgIter* __restrict__ rin,
+                                                             CgIter* __restrict__ rout,
+                                                             const double* __restrict__ part_in,
+                                                             double* __restrict__ part_out, int cur, double tol2,
+                                                             int first, int* __restrict__ done_flag) {
+    __shared__ double sh_u[6];
+    __shared__ double sh_ab[2];
+    __shared__ int sh_done;
+    if (rin->done) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            *rout = *rin;
+            if (done_flag) *done_flag = 1;
+        }
+        return;
+    }
+    const int N = g.H * g.W;
+    const int round = kCgThreads * kCgPx;
+    int rb = cg_range(blockIdx.x, gridDim.x);
+    CgPix a[kCgPx];
+#pragma unroll
+    for (int j = 0; j < kCgPx; ++j) {
+        const int i = rb * round + j * kCgThreads + threadIdx.x;
+        if (i < N) cg_load(g, P, act, cur, first != 0, i, a[j]);
+    }
+    double tot[kCgPartials];
+    final_sum<kCgPartials, kCgThreads>(part_in, gridDim.x, tot);
+    if (threadIdx.x == 0) {
+        CgIter st = *rin;
+        double w[6];
+        sym6_mul(cs->A, st.u, w);
+        for (int k = 0; k < 6; ++k) w[k] += tot[3 + k];
+        const double gamma = tot[0] + dot6(st.r, st.u);
+        const double delta = tot[1] + dot6(w, st.u);
+        const double rr = tot[2] + dot6(st.r, st.r);
+        if (!first) {
+            st.iters += 1;
+            if (rr <= tol2 * cs->rr0) st.done = 1;
+        }
+        st.rr = rr;
+        double alpha = 0.0, beta = 0.0;
+        if (!st.done) {
+            beta = first ? 0.0 : gamma / st.gamma;
+            alpha = first ? gamma / delta : gamma / (delta - beta * gamma / st.alpha);
+            for (int k = 0; k < 6; ++k) {
+                st.p[k] = first ? st.u[k] : fma(beta, st.p[k], st.u[k]);
+                st.s[k] = first ? w[k] : fma(beta, st.s[k], w[k]);
+                st.x[k] = fma(alpha, st.p[k], st.x[k]);
+                st.r[k] = fma(-alpha, st.s[k], st.r[k]);
+            }
+            sym6_mul(cs->Ainv, st.r, st.u);
+            st.gamma = gamma;
+            st.alpha = alpha;
+        }
+        for (int k = 0; k < 6; ++k) sh_u[k] = st.u[k];
+        sh_ab[0] = alpha;
+        sh_ab[1] = beta;
+        sh_done = st.done;
+        if (blockIdx.x == 0) {
+            *rout = st;
+            if (done_flag) *done_flag = st.done;
+        }
+    }
+    __syncthreads();
+    if (sh_done) return;
+    const double alpha = sh_ab[0], beta = sh_ab[1], lamN = s.lamN;
+    const int nxt = 1 - cur;
+    double up[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) up[k] = sh_u[k];
+    double red[kCgPartials];
+#pragma unroll
+    for (int k = 0; k < kCgPartials; ++k) red[k] = 0.0;
+    while (true) {
+#pragma unroll
+        for (int j = 0; j < kCgPx; ++j) {
+            const int i = rb * round + j * kCgThreads + threadIdx.x;
+            if (i >= N) continue;
+            const CgPix& c = a[j];
+            const long pi = pix_of(g, c.u, c.v);
+            double un[4];
+            const int ea = lamN > 0.0 ? c.act : 0;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                un[d] = 0.0;
+                if (ea & (1 << d)) {
+                    int nu, nv;
+                    neighbour(g, c.u, c.v, d, nu, nv);
+                    const long pj = pix_of(g, nu, nv);
+                    double sj;
+                    const double rj = cg_new_r(P.r[cur][pj], P.w[cur][pj], first ? 0.0 : P.s[cur][pj], alpha, beta,
+                                               first != 0, sj);
+                    un[d] = rj / P.diag[pj];
+                }
+            }
+            const double u_old = c.r / c.diag;
+            const double pn = first ? u_old : fma(beta, c.p, u_old);
+            double sv;
+            const double r = cg_new_r(c.r, c.w, c.s, alpha, beta, first != 0, sv);
+            double w;
+            cg_apply_pixel(c.diag, c.b, un, ea, lamN, up, r, r / c.diag, w, red);
+            P.x[pi] = fma(alpha, pn, c.x);
+            P.p[pi] = pn;
+            P.s[nxt][pi] = sv;
+            P.r[nxt][pi] = r;
+            P.w[nxt][pi] = w;
+        }
+        rb += gridDim.x;
+        if (rb * round >= N) break;
+#pragma unroll
+        for (int j = 0; j < kCgPx; ++j) {
+            const int i = rb * round + j * kCgThreads + threadIdx.x;
+            if (i < N) cg_load(g, P, act, cur, first != 0, i, a[j]);
+        }
+    }
+    block_reduce<kCgPartials, kCgThreads>(red, part_out);
+}
+
+// after the last launched iteration: the stop test of the last update (if the
+// solve had not stopped) and the solve's results into the solver state
+__global__ __launch_bounds__(kCgThreads) void k_c_cg_end(CgState* __restrict__ cs, const CgIter* __restrict__ rin,
+                                                         const double* __restrict__ part_in, int nbx, double tol2) {
+    CgIter st = *rin;
+    if (!st.done) {
+        double tot[kCgPartials];
+        final_sum<kCgPartials, kCgThreads>(part_in, nbx, tot);
+        st.rr = tot[2] + dot6(st.r, st.r);
+        st.iters += 1;
+        if (st.rr <= tol2 * cs->rr0) st.done = 1;
+    }
     if (threadIdx.x != 0) return;
-    const double rz = tot[0] + dot6(cs->r, cs->z);
-    const double rr = tot[1] + dot6(cs->r, cs->r);
-    cs->beta = rz / cs->rz;
-    cs->rz = rz;
-    cs->rr = rr;
-    for (int k = 0; k < 6; ++k) cs->p[k] = cs->z[k] + cs->beta * cs->p[k];
-    cs->iters += 1;
-    cs->total += 1;
-    if (rr <= tol2 * cs->rr0) cs->done = 1;
+    for (int k = 0; k < 6; ++k) cs->x[k] = st.x[k];
+    cs->rr = st.rr;
+    cs->done = st.done;
+    cs->iters = st.iters;
+    cs->total += st.iters;
 }
 
 __global__ void k_c_apply(Geo g, Planes P) {
@@ -413,7 +646,7 @@ struct pixvod_central {
     hipStream_t own_stream = nullptr, stream = nullptr;
     float *Is = nullptr, *cxt = nullptr, *cyt = nullptr, *It = nullptr, *Gx = nullptr, *Gy = nullptr;
     float *stage = nullptr, *out_stage = nullptr;
-    double* planes = nullptr;       // ell, diag, b (6), gl, x, r, z, p0, p1, q
+    double* planes = nullptr;       // ell, diag, b (6), gl, x, p, r (2), w (2), s (2)
     double* partial = nullptr;
     double* dense = nullptr;
     CgState* cs = nullptr;
@@ -422,10 +655,12 @@ struct pixvod_central {
     bool have_kf = false;
     double last_ms = 0.0;
     hipEvent_t ev[2] = {nullptr, nullptr};
-    // one IRLS iteration captured as a HIP graph on `graph_stream`
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    hipStream_t graph_stream = nullptr;
+    CgIter* rec = nullptr;          // the CG launches' two scalar records
+    double* part_cg = nullptr;      // their per-workgroup partial sums (two alternating buffers)
+    unsigned char* act = nullptr;   // active normal edges per pixel (bit per direction)
+    int* h_done = nullptr;          // pinned, coherent: the stop flag after each of the last two chunks
+    int* d_done = nullptr;          // its device address
+    hipEvent_t evc[2] = {nullptr, nullptr};
     std::string err;
 };
 
@@ -466,14 +701,15 @@ Planes cplanes(const pixvod_central* c) {
     P.b = b + 2 * pl;
     P.gl = b + 8 * pl;
     P.x = b + 9 * pl;
-    P.r = b + 10 * pl;
-    P.z = b + 11 * pl;
-    P.p0 = b + 12 * pl;
-    P.p1 = b + 13 * pl;
-    P.q = b + 14 * pl;
+    P.p = b + 10 * pl;
+    for (int k = 0; k < 2; ++k) {
+        P.r[k] = b + (11 + k) * pl;
+        P.w[k] = b + (13 + k) * pl;
+        P.s[k] = b + (15 + k) * pl;
+    }
     return P;
 }
-constexpr int kPlanes = 15;
+constexpr int kPlanes = 17;
 
 Inputs cinputs(const pixvod_central* c) {
     Inputs in;
@@ -490,15 +726,16 @@ Inputs cinputs(const pixvod_central* c) {
 dim3 cgrid(const Geo& g) { return dim3((g.W + 63) / 64, (g.H + 3) / 4); }
 
 void crelease(pixvod_central* c) {
-    void* bufs[] = {c->Is, c->cxt, c->cyt, c->It, c->Gx, c->Gy, c->stage, c->out_stage, c->planes, c->partial,
-                    c->dense, c->cs};
+    void* bufs[] = {c->Is,     c->cxt,   c->cyt,   c->It,      c->Gx,         c->Gy,    c->stage, c->out_stage,
+                    c->planes, c->partial, c->dense, c->cs, c->rec, c->part_cg, c->act};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (c->h_cs) (void)hipHostFree(c->h_cs);
+    if (c->h_done) (void)hipHostFree(c->h_done);
     for (hipEvent_t e : c->ev)
         if (e) (void)hipEventDestroy(e);
-    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
+    for (hipEvent_t e : c->evc)
+        if (e) (void)hipEventDestroy(e);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
 }
 
@@ -557,9 +794,19 @@ int pixvod_central_create(int H, int W, const pixvod_intrinsics* K, const pixvod
     if (!rc) rc = calloc_dev(c, &c->partial, (size_t)c->nb * kLinPartials);
     if (!rc) rc = calloc_dev(c, &c->dense, N);
     if (!rc) rc = calloc_dev(c, &c->cs, 1);
+    if (!rc) rc = calloc_dev(c, &c->rec, 2);
+    if (!rc) rc = calloc_dev(c, &c->part_cg, (size_t)2 * kCgMaxBlocks * kCgPartials);
     if (!rc && hipHostMalloc((void**)&c->h_cs, sizeof(CgState)) != hipSuccess) rc = cfail(c, PIXVOD_ENOMEM, "pinned allocation failed");
+    if (!rc) rc = calloc_dev(c, &c->act, pl);
+    if (!rc && (hipHostMalloc((void**)&c->h_done, 2 * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent) !=
+                    hipSuccess ||
+                hipHostGetDevicePointer((void**)&c->d_done, c->h_done, 0) != hipSuccess))
+        rc = cfail(c, PIXVOD_ENOMEM, "pinned allocation failed");
     if (!rc && hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess) rc = PIXVOD_EHIP;
     if (!rc && (hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess)) rc = PIXVOD_EHIP;
+    if (!rc && (hipEventCreateWithFlags(&c->evc[0], hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&c->evc[1], hipEventDisableTiming) != hipSuccess))
+        rc = PIXVOD_EHIP;
     if (rc) {
         std::string m = c->err.empty() ? "allocation failed" : c->err;
         crelease(c);
@@ -612,6 +859,7 @@ int pixvod_central_set_keyframe(pixvod_central* c, const float* img, const float
     }
     const Geo g = cgeo(c);
     hipLaunchKernelGGL(k_c_keyframe, cgrid(g), dim3(64, 4), 0, c->stream, g, di, dn, c->Is, c->cxt, c->cyt);
+    hipLaunchKernelGGL(k_c_edges, cgrid(g), dim3(64, 4), 0, c->stream, g, cinputs(c), c->act);
     C_TRY(c, hipGetLastError());
     // the pose restarts at the identity; log-depths are kept
     for (int k = 0; k < 6; ++k) c->h_cs->xi[k] = 0.0;
@@ -679,51 +927,45 @@ int pixvod_central_track(pixvod_central* c, const float* frame, int where, int n
     const Planes P = cplanes(c);
     const dim3 gr = cgrid(g), blk(64, 4);
     const double tol2 = c->tol * c->tol;
-    // one IRLS iteration: linearise, max_cg CG iterations (the launches after
-    // convergence return at once), apply the step
-    auto irls_iteration = [&](hipStream_t st) {
+    const long round = (long)kCgThreads * kCgPx;
+    const int nbx = (int)std::min<long>(((long)N + 8 * round - 1) / (8 * round) * 8, kCgMaxBlocks);
+    double* part[2] = {c->part_cg, c->part_cg + (size_t)kCgMaxBlocks * kCgPartials};
+    const hipStream_t st = c->stream;
+    hipLaunchKernelGGL(k_c_reset_total, dim3(1), dim3(64), 0, st, c->cs);
+    C_TRY(c, hipEventRecord(c->ev[0], st));
+    for (int it = 0; it < n_iters; ++it) {
+        // linearise, CG start, then CG iterations in chunks: the last launch of
+        // chunk j writes the stop flag to host memory; after launching chunk
+        // j the host waits for chunk j - 1's (chunk j keeps the device busy
+        // meanwhile)
         hipLaunchKernelGGL(k_c_linearise, gr, blk, 0, st, g, s, in, c->cs, P, c->partial);
-        hipLaunchKernelGGL(k_c_lin_final, dim3(1), dim3(kThreads), 0, st, s, c->nb, c->partial, c->cs);
-        for (int k = 0; k < c->max_cg; ++k) {
-            const double* pin = (k & 1) ? P.p1 : P.p0;
-            double* pout = (k & 1) ? P.p0 : P.p1;
-            hipLaunchKernelGGL(k_c_matvec, gr, blk, 0, st, g, s, in, c->cs, P, pin, pout, c->partial);
-            hipLaunchKernelGGL(k_c_alpha, dim3(1), dim3(kThreads), 0, st, c->nb, c->partial, c->cs);
-            hipLaunchKernelGGL(k_c_update, gr, blk, 0, st, g, c->cs, P, pout, c->partial);
-            hipLaunchKernelGGL(k_c_beta, dim3(1), dim3(kThreads), 0, st, c->nb, c->partial, c->cs, tol2);
-        }
-        hipLaunchKernelGGL(k_c_apply, gr, blk, 0, st, g, P);
-        hipLaunchKernelGGL(k_c_apply_pose, dim3(1), dim3(64), 0, st, c->cs);
-    };
-    // captured once per stream as a graph (every argument is fixed for the
-    // solver's lifetime); plain launches if capture is unavailable
-    if (n_iters > 0 && c->graph_stream != c->stream) {
-        if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-        if (c->graph) (void)hipGraphDestroy(c->graph);
-        c->graph_exec = nullptr;
-        c->graph = nullptr;
-        c->graph_stream = nullptr;
-        if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-            irls_iteration(c->stream);
-            hipGraph_t gph = nullptr;
-            if (hipStreamEndCapture(c->stream, &gph) == hipSuccess && gph) {
-                hipGraphExec_t ex = nullptr;
-                if (hipGraphInstantiate(&ex, gph, nullptr, nullptr, 0) == hipSuccess) {
-                    c->graph = gph;
-                    c->graph_exec = ex;
-                    c->graph_stream = c->stream;
-                } else {
-                    (void)hipGraphDestroy(gph);
-                }
+        hipLaunchKernelGGL(k_c_lin_final, dim3(1), dim3(kThreads), 0, st, s, c->nb, c->partial, c->cs, c->rec);
+        hipLaunchKernelGGL(k_c_cg_init, dim3(nbx), dim3(kCgThreads), 0, st, g, s, P, c->act, c->rec, part[0]);
+        C_TRY(c, hipGetLastError());
+        int launched = 0;
+        for (int chunk = 0; launched < c->max_cg; ++chunk) {
+            const int n = std::min(kCgChunk, c->max_cg - launched);
+            const bool last = launched + n >= c->max_cg;
+            for (int k = launched; k < launched + n; ++k) {
+                const int cur = k & 1;
+                int* flag = (!last && k == launched + n - 1) ? c->d_done + (chunk & 1) : nullptr;
+                hipLaunchKernelGGL(k_c_cg_iter, dim3(nbx), dim3(kCgThreads), 0, st, g, s, c->cs, P, c->act,
+                                   c->rec + cur, c->rec + (1 - cur), part[cur], part[1 - cur], cur, tol2,
+                                   k == 0 ? 1 : 0, flag);
+            }
+            C_TRY(c, hipGetLastError());
+            launched += n;
+            if (last) break;
+            C_TRY(c, hipEventRecord(c->evc[chunk & 1], st));
+            if (chunk > 0) {
+                C_TRY(c, hipEventSynchronize(c->evc[(chunk - 1) & 1]));
+                if (c->h_done[(chunk - 1) & 1]) break;
             }
         }
-        (void)hipGetLastError();
-    }
-    hipLaunchKernelGGL(k_c_reset_total, dim3(1), dim3(64), 0, c->stream, c->cs);
-    C_TRY(c, hipEventRecord(c->ev[0], c->stream));
-    for (int it = 0; it < n_iters; ++it) {
-        if (c->graph_exec) C_TRY(c, hipGraphLaunch(c->graph_exec, c->stream));
-        else irls_iteration(c->stream);
+        hipLaunchKernelGGL(k_c_cg_end, dim3(1), dim3(kCgThreads), 0, st, c->cs, c->rec + (launched & 1),
+                           part[launched & 1], nbx, tol2);
+        hipLaunchKernelGGL(k_c_apply, gr, blk, 0, st, g, P);
+        hipLaunchKernelGGL(k_c_apply_pose, dim3(1), dim3(64), 0, st, c->cs);
         C_TRY(c, hipGetLastError());
     }
     C_TRY(c, hipEventRecord(c->ev[1], c->stream));

@@ -19,6 +19,11 @@ SOURCES = ["gbp_kernels.hip", "gbp_adjoint.hip", "gbp_tree.hip", "gbp_transfer.h
 ARCH = os.environ.get("PIXVOD_ARCH", "gfx950")
 
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Per-source flags. The persistent passes in gbp_kernels.hip loop over tiles
+# around a body that needs every register: hoisting loop-invariant values
+# (constants, addresses) out of such a loop only makes them spill, so machine
+# loop-invariant code motion is off there.
+SOURCE_FLAGS = {"gbp_kernels.hip": ["-mllvm", "-disable-machine-licm"]}
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-result"]
 
 
@@ -28,7 +33,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     procs = []
     for src in SOURCES:
         obj = os.path.join(CSRC, src.replace(".hip", ".o"))
-        cmd = [hipcc, *COMMON, *DEVICE_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc, *COMMON, *DEVICE_FLAGS, *SOURCE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd), cmd))

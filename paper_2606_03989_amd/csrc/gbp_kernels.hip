@@ -547,11 +547,38 @@ __device__ inline bool halo_point(const Geo& g, int u0, int v0, int l, int& u, i
     return u >= 0 && u < g.W && v >= 0 && v < g.H;
 }
 
-template <bool FINAL, bool SH>
+// The stored messages of a pixel (eta 6 and Lambda 21 of the four identity
+// slots, eta and lambda of the four normal slots) are the 116 consecutive
+// planes from P_MID. The persistent single-sequence pass keeps them for the
+// next 64 x 4 tile in LDS, loaded straight from memory into LDS (no
+// registers) while the current tile computes: wave w loads tile row w, plane
+// k of lane l at buf[k * 256 + w * 64 + l]. Lanes outside the image load any
+// valid pixel; their values are not used.
+constexpr int MSG_PLANES = 116;
+static_assert(P_MN + 8 == P_MID + MSG_PLANES, "messages are contiguous planes");
+
+__device__ inline void prefetch_messages(const Geo& g, const float* __restrict__ X, float* buf, int u0, int v0,
+                                         int w, int lane) {
+    const int u = u0 + lane, v = v0 + w;
+    const long p = (u < g.W && v < g.H) ? pix_of(g, u, v) : 0;
+    const float* src = X + (long)P_MID * g.plane + p;
+    float* dst = buf + w * 64;
+#pragma unroll 4
+    for (int k = 0; k < MSG_PLANES; ++k)
+        __builtin_amdgcn_global_load_lds((const void*)(src + (long)k * g.plane),
+                                         (__attribute__((address_space(3))) void*)(dst + k * 256), 4, 0, 0);
+}
+
+// wait for this wave's loads into LDS: the compiler does not track them, so
+// the wait is explicit, and the memory clobber keeps the LDS reads after it
+__device__ inline void wait_lds_loads() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+template <bool FINAL, bool SH, bool PIPE = false>
 __device__ __attribute__((always_inline)) inline void iterate_pixel_pf(
     const Geo& g, const Strengths& s, const Inputs& in, const float* __restrict__ X, float* __restrict__ Y,
     float* __restrict__ var_ll, float* __restrict__ valid, int* __restrict__ health, int u, int v,
-    bool inside = true, double* __restrict__ sh = nullptr, int u0 = 0, int v0 = 0, int tid = 0) {
+    bool inside = true, double* __restrict__ sh = nullptr, int u0 = 0, int v0 = 0, int tid = 0,
+    float* mbuf = nullptr, bool pre = false, int nu0 = 0, int nv0 = 0) {
     const long p = inside ? pix_of(g, u, v) : 0;
     bool has[4];
     long pn[4];
@@ -575,18 +602,31 @@ __device__ __attribute__((always_inline)) inline void iterate_pixel_pf(
 #pragma unroll
                 for (int k = 0; k < 7; ++k) npt[d][k] = X[(long)(P_TAU + k) * g.plane + pn[d]];
         }
+        if constexpr (!PIPE) {
 #pragma unroll
-        for (int d = 0; d < 4; ++d) {
+            for (int d = 0; d < 4; ++d) {
 #pragma unroll
-            for (int k = 0; k < 27; ++k) mid[d][k] = X[(long)(P_MID + d * MID_STRIDE + k) * g.plane + p];
-            mn[d][0] = X[(long)(P_MN + 2 * d) * g.plane + p];
-            mn[d][1] = X[(long)(P_MN + 2 * d + 1) * g.plane + p];
+                for (int k = 0; k < 27; ++k) mid[d][k] = X[(long)(P_MID + d * MID_STRIDE + k) * g.plane + p];
+                mn[d][0] = X[(long)(P_MN + 2 * d) * g.plane + p];
+                mn[d][1] = X[(long)(P_MN + 2 * d + 1) * g.plane + p];
+            }
         }
         ct.c[DIR_L] = in.cxt[pn[DIR_L]];
         ct.c[DIR_R] = in.cxt[p];
         ct.c[DIR_U] = in.cyt[pn[DIR_U]];
         ct.c[DIR_D] = in.cyt[p];
         pin = load_pixel_inputs(g, s, in, u, v);
+        if constexpr (PIPE) {
+            // this tile's messages, prefetched into LDS during the previous tile
+            wait_lds_loads();
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+#pragma unroll
+                for (int k = 0; k < 27; ++k) mid[d][k] = mbuf[(d * MID_STRIDE + k) * 256 + tid];
+                mn[d][0] = mbuf[(P_MN - P_MID + 2 * d) * 256 + tid];
+                mn[d][1] = mbuf[(P_MN - P_MID + 2 * d + 1) * 256 + tid];
+            }
+        }
 #pragma unroll
         for (int k = 0; k < 6; ++k) tau[k] = (double)pt[k];
         ell = (double)pt[6];
@@ -607,11 +647,20 @@ __device__ __attribute__((always_inline)) inline void iterate_pixel_pf(
         }
         __syncthreads();
     }
-    if (!inside) return;
+    if (!inside) {
+        if constexpr (PIPE) {
+            wait_lds_loads();   // this lane's slots of the buffer are read (nothing) before they are refilled
+            if (pre) prefetch_messages(g, X, mbuf, nu0, nv0, tid >> 6, tid & 63);
+        }
+        return;
+    }
 
     // --- linearise at the current point
     double L[28], eta[7];
     const bool val = unary_factors(g, s, in, u, v, tau, R, t, ell, pin, L, eta);
+    if constexpr (PIPE && FINAL) {
+        if (pre) prefetch_messages(g, X, mbuf, nu0, nv0, tid >> 6, tid & 63);
+    }
 
     // --- complete the partials in flight (complete_partials)
     const int hown = SH ? (v - v0 + 1) * HALO_W + (u - u0 + 1) : 0;
@@ -673,6 +722,10 @@ __device__ __attribute__((always_inline)) inline void iterate_pixel_pf(
         // --- linearise at the new point and send the next partials (emit_partials)
         se3_exp(tau, R, t);
         unary_factors(g, s, in, u, v, tau, R, t, ell, pin, L, eta);
+        if constexpr (PIPE) {
+            // the next tile's messages stream into LDS during the rest of this one
+            if (pre) prefetch_messages(g, X, mbuf, nu0, nv0, tid >> 6, tid & 63);
+        }
         add_messages(L, eta, mid, mn);
         double P[21], pm[6], D, dv;
         pose_marginal(L, eta, P, pm);
@@ -716,17 +769,52 @@ __global__ __launch_bounds__(256) void k_fu_prologue(Geo g, Strengths s, Inputs 
     prologue_pixel(g, s, in, X, Y, health, u, v);
 }
 
-// one 64 x 4 tile per workgroup; every lane reaches the barrier of the shared
-// table, lanes outside the image only help fill it
+// Persistent: each workgroup (one per CU: the LDS of the shared table and the
+// message buffer fill a CU) takes the 64 x 4 tiles blockIdx, blockIdx +
+// gridDim, ... in turn, loading the next tile's messages into LDS while it
+// computes the current one. Every lane reaches the barriers of every tile;
+// lanes outside the image only help fill the shared table.
 template <bool FINAL>
 __global__ __launch_bounds__(256) void k_fu_iterate(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
                                                     float* __restrict__ Y, float* __restrict__ var_ll,
-                                                    float* __restrict__ valid, int* __restrict__ health) {
+                                                    float* __restrict__ valid, int* __restrict__ health,
+                                                    int tiles_x, int ntiles) {
     __shared__ double sh[SH_FIELDS * HALO_N];
-    const int u0 = blockIdx.x * 64, v0 = blockIdx.y * 4;
-    const int u = u0 + threadIdx.x, v = v0 + threadIdx.y;
-    iterate_pixel_pf<FINAL, true>(g, s, in, X, Y, var_ll, valid, health, u, v, u < g.W && v < g.H, sh, u0, v0,
-                                  threadIdx.y * 64 + threadIdx.x);
+    __shared__ float mbuf[MSG_PLANES * 256];
+    const int tid = threadIdx.y * 64 + threadIdx.x;
+    int tile = blockIdx.x;
+    if (tile >= ntiles) return;
+    prefetch_messages(g, X, mbuf, (tile % tiles_x) * 64, (tile / tiles_x) * 4, threadIdx.y, threadIdx.x);
+    for (; tile < ntiles; tile += gridDim.x) {
+        const int next = tile + gridDim.x;
+        const int u0 = (tile % tiles_x) * 64, v0 = (tile / tiles_x) * 4;
+        const int u = u0 + threadIdx.x, v = v0 + threadIdx.y;
+        // everything the pass derives from the arguments and the lane index is
+        // made opaque per tile, so the compiler recomputes it inside the tile
+        // instead of hoisting it out of the loop (hundreds of plane and LDS
+        // addresses, which would not fit in registers)
+        int z = 0;
+        asm volatile("" : "+s"(z));
+        Geo gt = g;
+        gt.H += z;
+        gt.W += z;
+        gt.pitch += z;
+        gt.plane += z;
+        Inputs it = in;
+        it.Is += z;
+        it.cxt += z;
+        it.cyt += z;
+        it.sigD += z;
+        it.It += z;
+        it.Gx += z;
+        it.Gy += z;
+        it.prior_ell += z;
+        const int tz = tid + z;
+        __syncthreads();   // the previous tile's readers of the shared table are done
+        iterate_pixel_pf<FINAL, true, true>(gt, s, it, X + z, Y + z, var_ll + z, valid + z, health, u + z, v + z,
+                                            u < g.W && v < g.H, sh, u0, v0, tz, mbuf, next < ntiles,
+                                            (next % tiles_x) * 64, (next / tiles_x) * 4);
+    }
 }
 
 // the same passes for the reverse sweep's recompute: the prologue also writes
@@ -1158,10 +1246,22 @@ hipError_t launch_fu_prologue(const Geo& g, const Strengths& s, const Inputs& in
 
 hipError_t launch_fu_iterate(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* Y,
                              bool final_pass, float* var_ll, float* valid, int* health, hipStream_t st) {
+    static int n_cu = 0;
+    if (n_cu == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1)
+            n_cu = 256;
+    }
+    const dim3 t = grid2d(g, kBlockFused);
+    const int ntiles = (int)(t.x * t.y);
+    const dim3 grid((unsigned)std::min(ntiles, n_cu));
     if (final_pass)
-        hipLaunchKernelGGL(k_fu_iterate<true>, grid2d(g, kBlockFused), kBlockFused, 0, st, g, s, in, X, Y, var_ll, valid, health);
+        hipLaunchKernelGGL(k_fu_iterate<true>, grid, kBlockFused, 0, st, g, s, in, X, Y, var_ll, valid, health,
+                           (int)t.x, ntiles);
     else
-        hipLaunchKernelGGL(k_fu_iterate<false>, grid2d(g, kBlockFused), kBlockFused, 0, st, g, s, in, X, Y, var_ll, valid, health);
+        hipLaunchKernelGGL(k_fu_iterate<false>, grid, kBlockFused, 0, st, g, s, in, X, Y, var_ll, valid, health,
+                           (int)t.x, ntiles);
     return hipGetLastError();
 }
 

@@ -20,12 +20,12 @@ struct PoseBar {
 // existing slot of Xb by its reader
 // M: the tape of the new messages' information, LAM_STRIDE FP32 planes per slot
 hipError_t launch_adj_update(const Geo& g, const Strengths& s, const Inputs& in, const float* X, const float* M,
-                             const double* bel, const float* Xb, const float* Cb, double* Mb, double* Ub,
+                             const double* bel, const float* Xb, const float* Cb, float* Mb, float* Ub,
                              hipStream_t st);
 hipError_t launch_adj_edges(const Geo& g, const Strengths& s, const Inputs& in, const float* X, const double* marg,
-                            const float* M, const double* Mb, float* Xbo, double* Eb, double* gN, hipStream_t st);
+                            const float* M, const float* Mb, float* Xbo, float* Eb, double* gN, hipStream_t st);
 hipError_t launch_adj_belief(const Geo& g, const Strengths& s, const Inputs& in, const float* X, const double* marg,
-                             const double* Ub, const double* Eb, float* Xbo, float* Cbo, double* gsig, double* gk,
+                             const float* Ub, const float* Eb, float* Xbo, float* Cbo, double* gsig, double* gk,
                              hipStream_t st);
 hipError_t launch_adj_inject(const Geo& g, const float* Xend, float* Xb, const PoseBar& xb, const float* rhob,
                              hipStream_t st);

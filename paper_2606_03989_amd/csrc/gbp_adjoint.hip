@@ -1,6 +1,7 @@
 // HIP kernels of the reverse sweep through unrolled GBP iterations (PixVOD,
-// arXiv 2606.03989) for gfx950: one lane per pixel, FP32 cotangent planes in
-// the state layout, FP64 algebra in registers.
+// arXiv 2606.03989) for gfx950: one lane per pixel, FP32 cotangent planes (the
+// state's cotangent in the state layout and the intermediate ones: Mb, Ub,
+// Eb), FP64 algebra in registers.
 //
 // Reverse of one canonical iteration X -> X' (linearise + marginals, messages,
 // update + relinearise + transport; Sec. 3.4 and Sec. 4.1), given the
@@ -53,7 +54,7 @@ __device__ inline bool pixel_2d(const Geo& g, int& u, int& v) {
 __global__ __launch_bounds__(256, 2) void k_adj_update(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
                                                     const float* __restrict__ M, const double* __restrict__ bel,
                                                     const float* __restrict__ Xb, const float* __restrict__ Cb,
-                                                    double* __restrict__ Mb, double* __restrict__ Ub) {
+                                                    float* __restrict__ Mb, float* __restrict__ Ub) {
     int u, v;
     if (!pixel_2d(g, u, v)) return;
     const long p = pix_of(g, u, v);
@@ -120,11 +121,11 @@ __global__ __launch_bounds__(256, 2) void k_adj_update(Geo g, Strengths s, Input
     // cotangents of the four new messages: transport + belief
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
-        double* o = Mb + (long)d * MSG_STRIDE * pl + p;
+        float* o = Mb + (long)d * MSG_STRIDE * pl + p;
         int nu, nv;
         if (!neighbour(g, u, v, d, nu, nv)) {
 #pragma unroll
-            for (int k = 0; k < MSG_STRIDE; ++k) o[k * pl] = 0.0;
+            for (int k = 0; k < MSG_STRIDE; ++k) o[k * pl] = 0.0f;
             continue;
         }
         const float* xb = Xb + (long)(P_MID + d * MID_STRIDE) * pl + p;
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_update(Geo g, Strengths s, Input
 #pragma unroll
         for (int a = 0; a < 6; ++a) {
             eb[a] = (double)xb[a * pl] + (double)cb[a * pl];
-            o[a * pl] = eb[a] + betab[a];
+            o[a * pl] = (float)(eb[a] + betab[a]);
         }
 #pragma unroll
         for (int r = 0; r < 6; ++r)
@@ -141,21 +142,21 @@ __global__ __launch_bounds__(256, 2) void k_adj_update(Geo g, Strengths s, Input
             for (int c = r; c < 6; ++c) {
                 const double tr = (r == c) ? eb[r] * m[r] : eb[r] * m[c] + eb[c] * m[r];
                 o[(6 + s6(r, c)) * pl] =
-                    ((double)xb[(6 + s6(r, c)) * pl] + (double)cb[(6 + s6(r, c)) * pl]) - tr + Bb[s7(r, c)];
+                    (float)(((double)xb[(6 + s6(r, c)) * pl] + (double)cb[(6 + s6(r, c)) * pl]) - tr + Bb[s7(r, c)]);
             }
         const double neb = (double)Xb[(long)(P_MN + 2 * d) * pl + p] + (double)cb[27 * pl];
         const double nlb = (double)Xb[(long)(P_MN + 2 * d + 1) * pl + p] + (double)cb[28 * pl];
-        o[27 * pl] = neb + betab[6];
-        o[28 * pl] = nlb - neb * m[6] + Bb[s7(6, 6)];
+        o[27 * pl] = (float)(neb + betab[6]);
+        o[28 * pl] = (float)(nlb - neb * m[6] + Bb[s7(6, 6)]);
     }
-    double* ub = Ub + p;
+    float* ub = Ub + p;
 #pragma unroll
-    for (int k = 0; k < 28; ++k) ub[k * pl] = Bb[k];
+    for (int k = 0; k < 28; ++k) ub[k * pl] = (float)Bb[k];
 #pragma unroll
-    for (int k = 0; k < 7; ++k) ub[(28 + k) * pl] = betab[k];
+    for (int k = 0; k < 7; ++k) ub[(28 + k) * pl] = (float)betab[k];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) ub[(UB_TAU + k) * pl] = taub[k];
-    ub[UB_ELL * pl] = ellnb;
+    for (int k = 0; k < 6; ++k) ub[(UB_TAU + k) * pl] = (float)taub[k];
+    ub[UB_ELL * pl] = (float)ellnb;
 }
 
 // reverse of the message step (k_pf_messages), one lane per (pixel j,
@@ -167,8 +168,8 @@ __global__ __launch_bounds__(256, 2) void k_adj_update(Geo g, Strengths s, Input
 // Writes the sender part of j's slot-d cotangent to Xbo.
 __global__ __launch_bounds__(256, 2) void k_adj_edges(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
                                                    const double* __restrict__ marg, const float* __restrict__ M,
-                                                   const double* __restrict__ Mb, float* __restrict__ Xbo,
-                                                   double* __restrict__ Eb, double* __restrict__ gN) {
+                                                   const float* __restrict__ Mb, float* __restrict__ Xbo,
+                                                   float* __restrict__ Eb, double* __restrict__ gN) {
     const int d = threadIdx.x & 3;
     const int u = blockIdx.x * (blockDim.x >> 2) + (threadIdx.x >> 2);
     const int v = blockIdx.y;
@@ -191,9 +192,9 @@ __global__ __launch_bounds__(256, 2) void k_adj_edges(Geo g, Strengths s, Inputs
         const long pi = pix_of(g, nu, nv);
         const int o = opposite(d);
         const float* Mj = M + (long)d * LAM_STRIDE * pl + pj;
-        const double* Mbj = Mb + (long)d * MSG_STRIDE * pl + pj;
+        const float* Mbj = Mb + (long)d * MSG_STRIDE * pl + pj;
         const float* Mi = M + (long)o * LAM_STRIDE * pl + pi;
-        const double* Mbi = Mb + (long)o * MSG_STRIDE * pl + pi;
+        const float* Mbi = Mb + (long)o * MSG_STRIDE * pl + pi;
         // residual of the message into j from i, r = Log(Exp(tau_i)^-1 Exp(tau_j));
         // the message into i from j uses -r
         double ti[6], elli, Ri[9], tri[3], r[6];
@@ -208,12 +209,12 @@ __global__ __launch_bounds__(256, 2) void k_adj_edges(Geo g, Strengths s, Inputs
 #pragma unroll
             for (int k = 0; k < 21; ++k) Lam[k] = (double)Mj[k * pl];
 #pragma unroll
-            for (int a = 0; a < 6; ++a) e[a] = Mbj[a * pl];
+            for (int a = 0; a < 6; ++a) e[a] = (double)Mbj[a * pl];
             sym_mv6(Lam, e, y1);
 #pragma unroll
             for (int k = 0; k < 21; ++k) Lam[k] = (double)Mi[k * pl];
 #pragma unroll
-            for (int a = 0; a < 6; ++a) e[a] = Mbi[a * pl];
+            for (int a = 0; a < 6; ++a) e[a] = (double)Mbi[a * pl];
             sym_mv6(Lam, e, y2);
 #pragma unroll
             for (int a = 0; a < 6; ++a) rb[a] = y2[a] - y1[a];
@@ -226,12 +227,12 @@ __global__ __launch_bounds__(256, 2) void k_adj_edges(Geo g, Strengths s, Inputs
 #pragma unroll
         for (int k = 0; k < 21; ++k) {
             V[k] = marg[(long)k * pl + pj] - (double)X[(long)(P_MID + d * MID_STRIDE + 6 + k) * pl + pj];
-            Lpb[k] = Mbi[(6 + k) * pl];
+            Lpb[k] = (double)Mbi[(6 + k) * pl];
         }
 #pragma unroll
         for (int a = 0; a < 6; ++a) {
             vv[a] = marg[(long)(21 + a) * pl + pj] - (double)X[(long)(P_MID + d * MID_STRIDE + a) * pl + pj];
-            hb[a] = Mbi[a * pl];
+            hb[a] = (double)Mbi[a * pl];
         }
         // eta_i = h - Lp (-r): Lp_bar += sym(hb r^T)
         sym_outer_acc6(Lpb, hb, r, 1.0);
@@ -253,8 +254,8 @@ __global__ __launch_bounds__(256, 2) void k_adj_edges(Geo g, Strengths s, Inputs
         if (s.lamN > 0.0 && normal_residual(g, in, pj, pi, d, ell, elli, rn_j)) {
             normal_residual(g, in, pi, pj, o, elli, ell, rn_i);
             // ne_new = h - lp rn: receiver j and sender j (rn_i depends on ell_j with -1)
-            acc[35] = -(double)Mj[21 * pl] * Mbj[27 * pl] + (double)Mi[21 * pl] * Mbi[27 * pl];
-            const double neb = Mbi[27 * pl], nlb = Mbi[28 * pl];
+            acc[35] = -(double)Mj[21 * pl] * (double)Mbj[27 * pl] + (double)Mi[21 * pl] * (double)Mbi[27 * pl];
+            const double neb = (double)Mbi[27 * pl], nlb = (double)Mbi[28 * pl];
             const double ls = marg[27L * pl + pj] - (double)X[(long)(P_MN + 2 * d + 1) * pl + pj];
             const double vs = marg[28L * pl + pj] - (double)X[(long)(P_MN + 2 * d) * pl + pj];
             double lsb, vsb, lnb;
@@ -280,17 +281,17 @@ __global__ __launch_bounds__(256, 2) void k_adj_edges(Geo g, Strengths s, Inputs
         acc[k] += __shfl_xor(acc[k], 2, 4);
     }
     if (d == 0 && inside) {
-        double* eb = Eb + pj;
+        float* eb = Eb + pj;
 #pragma unroll
-        for (int k = 0; k < 21; ++k) eb[(EB_P + k) * pl] = acc[k];
+        for (int k = 0; k < 21; ++k) eb[(EB_P + k) * pl] = (float)acc[k];
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            eb[(EB_PV + k) * pl] = acc[21 + k];
-            eb[(EB_EPS + k) * pl] = acc[29 + k];
+            eb[(EB_PV + k) * pl] = (float)acc[21 + k];
+            eb[(EB_EPS + k) * pl] = (float)acc[29 + k];
         }
-        eb[EB_D * pl] = acc[27];
-        eb[EB_DV * pl] = acc[28];
-        eb[EB_ELL * pl] = acc[35];
+        eb[EB_D * pl] = (float)acc[27];
+        eb[EB_DV * pl] = (float)acc[28];
+        eb[EB_ELL * pl] = (float)acc[35];
         gN[pj] += acc[36];
     }
 }
@@ -298,8 +299,8 @@ __global__ __launch_bounds__(256, 2) void k_adj_edges(Geo g, Strengths s, Inputs
 // reverse of the marginals and of the unary factors; completes Xbo (point
 // planes) and writes the slot-common part Cbo
 __global__ __launch_bounds__(256) void k_adj_belief(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
-                                                    const double* __restrict__ marg, const double* __restrict__ Ub,
-                                                    const double* __restrict__ Eb,
+                                                    const double* __restrict__ marg, const float* __restrict__ Ub,
+                                                    const float* __restrict__ Eb,
                                                     float* __restrict__ Xbo, float* __restrict__ Cbo,
                                                     double* __restrict__ gsig, double* __restrict__ gk) {
     int u, v;
@@ -314,31 +315,31 @@ __global__ __launch_bounds__(256) void k_adj_belief(Geo g, Strengths s, Inputs i
     for (int k = 0; k < 28; ++k) L[k] = marg[(long)(29 + k) * pl + p];
 #pragma unroll
     for (int k = 0; k < 7; ++k) eta[k] = marg[(long)(57 + k) * pl + p];
-    const double* eb = Eb + p;
+    const float* eb = Eb + p;
     double Pb[21], pb[6];
 #pragma unroll
-    for (int k = 0; k < 21; ++k) Pb[k] = eb[(EB_P + k) * pl];
+    for (int k = 0; k < 21; ++k) Pb[k] = (double)eb[(EB_P + k) * pl];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) pb[k] = eb[(EB_PV + k) * pl];
+    for (int k = 0; k < 6; ++k) pb[k] = (double)eb[(EB_PV + k) * pl];
     double BbS[28], ebS[7];
 #pragma unroll
     for (int k = 0; k < 28; ++k) BbS[k] = 0.0;
 #pragma unroll
     for (int k = 0; k < 7; ++k) ebS[k] = 0.0;
-    marginals_adjoint(L, eta, Pb, pb, eb[EB_D * pl], eb[EB_DV * pl], BbS, ebS);
+    marginals_adjoint(L, eta, Pb, pb, (double)eb[EB_D * pl], (double)eb[EB_DV * pl], BbS, ebS);
 
-    const double* ub = Ub + p;
+    const float* ub = Ub + p;
     double Lb[28], etab[7], epsb[6], taub[6];
 #pragma unroll
-    for (int k = 0; k < 28; ++k) Lb[k] = ub[k * pl] + BbS[k];
+    for (int k = 0; k < 28; ++k) Lb[k] = (double)ub[k * pl] + BbS[k];
 #pragma unroll
-    for (int k = 0; k < 7; ++k) etab[k] = ub[(28 + k) * pl] + ebS[k];
+    for (int k = 0; k < 7; ++k) etab[k] = (double)ub[(28 + k) * pl] + ebS[k];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        epsb[k] = eb[(EB_EPS + k) * pl];
-        taub[k] = ub[(UB_TAU + k) * pl];
+        epsb[k] = (double)eb[(EB_EPS + k) * pl];
+        taub[k] = (double)ub[(UB_TAU + k) * pl];
     }
-    double ellb = ub[UB_ELL * pl] + eb[EB_ELL * pl];
+    double ellb = (double)ub[UB_ELL * pl] + (double)eb[EB_ELL * pl];
     double sigb = 0.0, kb = 0.0;
     unary_adjoint(g, s, in, u, v, tau, R, t, ell, Lb, etab, epsb, taub, ellb, sigb, kb);
     double te[6];
@@ -427,14 +428,14 @@ static const dim3 kAdjBlock(64, 4);
 static dim3 adj_grid(const Geo& g) { return dim3((g.W + 63) / 64, (g.H + 3) / 4); }
 
 hipError_t launch_adj_update(const Geo& g, const Strengths& s, const Inputs& in, const float* X, const float* M,
-                             const double* bel, const float* Xb, const float* Cb, double* Mb, double* Ub,
+                             const double* bel, const float* Xb, const float* Cb, float* Mb, float* Ub,
                              hipStream_t st) {
     hipLaunchKernelGGL(k_adj_update, adj_grid(g), kAdjBlock, 0, st, g, s, in, X, M, bel, Xb, Cb, Mb, Ub);
     return hipGetLastError();
 }
 
 hipError_t launch_adj_edges(const Geo& g, const Strengths& s, const Inputs& in, const float* X, const double* marg,
-                            const float* M, const double* Mb, float* Xbo, double* Eb, double* gN, hipStream_t st) {
+                            const float* M, const float* Mb, float* Xbo, float* Eb, double* gN, hipStream_t st) {
     // one lane per (pixel, direction): 64 pixels of a row per 256-lane workgroup
     hipLaunchKernelGGL(k_adj_edges, dim3((g.W + 63) / 64, g.H), dim3(256), 0, st, g, s, in, X, marg, M, Mb, Xbo, Eb,
                        gN);
@@ -442,7 +443,7 @@ hipError_t launch_adj_edges(const Geo& g, const Strengths& s, const Inputs& in, 
 }
 
 hipError_t launch_adj_belief(const Geo& g, const Strengths& s, const Inputs& in, const float* X, const double* marg,
-                             const double* Ub, const double* Eb, float* Xbo, float* Cbo, double* gsig, double* gk,
+                             const float* Ub, const float* Eb, float* Xbo, float* Cbo, double* gsig, double* gk,
                              hipStream_t st) {
     hipLaunchKernelGGL(k_adj_belief, adj_grid(g), kAdjBlock, 0, st, g, s, in, X, marg, Ub, Eb, Xbo, Cbo, gsig, gk);
     return hipGetLastError();

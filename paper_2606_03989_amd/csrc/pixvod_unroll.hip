@@ -46,7 +46,8 @@ struct pixvod_unroll {
     float *frames = nullptr, *stage = nullptr;
     float *X0 = nullptr, *Xw[2] = {nullptr, nullptr}, *tape = nullptr, *Xend = nullptr, *seg = nullptr;
     float *var_ll = nullptr, *valid = nullptr;
-    double *marg = nullptr, *bel = nullptr, *Mb = nullptr, *Ub = nullptr, *Eb = nullptr;
+    double *marg = nullptr, *bel = nullptr;
+    float *Mb = nullptr, *Ub = nullptr, *Eb = nullptr;   // reverse-sweep cotangents, FP32 storage
     float* M = nullptr;
     // the reverse sweep recomputes the next segment on a side stream while
     // the current one is reversed: a second set of recompute buffers (and of
@@ -379,7 +380,7 @@ int pixvod_unroll_backward(pixvod_unroll* u, const double* xi_bar, const float* 
     // host cotangents of the inverse-depth maps are staged one frame at a
     // time into the Mb buffer, which the reverse kernels only overwrite after
     // the frame's injection has read it (stream order)
-    float* rho_stage = reinterpret_cast<float*>(u->Mb);
+    float* rho_stage = u->Mb;
     const Strengths s = ustrengths(u);
     const Inputs in = uinputs(u);
     UHIP(hipEventRecord(u->ev[2], u->stream));

@@ -11,8 +11,9 @@ struct Inputs;
 struct SeqDesc;
 struct BatchLaunch;
 
+// target frame and its gradients; `clear` (may be NULL) is set to 0 on the way
 hipError_t launch_frame_prep(const Geo& g, const float* src, long src_pitch, float* It, float* Gx, float* Gy,
-                             hipStream_t st);
+                             hipStream_t st, int* clear = nullptr);
 hipError_t launch_keyframe_prep(const Geo& g, const float* img, const float* normals, float* Is, float* cxt,
                                 float* cyt, float* X, float* X2, hipStream_t st);
 hipError_t launch_init_state(const Geo& g, float* X, float ell0, hipStream_t st);
@@ -32,8 +33,10 @@ hipError_t launch_fu_step_tape(const Geo& g, const Strengths& s, const Inputs& i
 hipError_t launch_valid_only(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* valid,
                              hipStream_t st);
 int stats_blocks(const Geo& g);
+// result (9 doubles): the six pose sums, valid count, non-finite count, and
+// the health flag *health when given
 hipError_t launch_frame_stats(const Geo& g, const float* X, const float* valid, int use_valid, double* partial,
-                              double* result, hipStream_t st);
+                              double* result, hipStream_t st, const int* health = nullptr);
 hipError_t launch_outputs(const Geo& g, const float* X, const float* var_ll, int have_var, float* inv_depth,
                           float* inv_var, hipStream_t st);
 hipError_t launch_pack_state(const Geo& g, const float* X, float* dense, int to_dense, hipStream_t st);

@@ -230,9 +230,10 @@ __device__ __attribute__((always_inline)) inline void frame_prep_pixel(const Geo
 }
 
 __global__ void k_frame_prep(Geo g, const float* __restrict__ src, long src_pitch, float* __restrict__ It,
-                             float* __restrict__ Gx, float* __restrict__ Gy) {
+                             float* __restrict__ Gx, float* __restrict__ Gy, int* __restrict__ clear) {
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
     const int v = blockIdx.y * blockDim.y + threadIdx.y;
+    if (clear && u == 0 && v == 0) *clear = 0;
     if (u >= g.W || v >= g.H) return;
     frame_prep_pixel(g, src, src_pitch, It, Gx, Gy, u, v);
 }
@@ -846,10 +847,28 @@ __global__ __launch_bounds__(256) void k_fu_final_tape(Geo g, Strengths s, Input
 constexpr int RED_THREADS = 256;
 
 // per block: sum of the six pose planes, valid count, non-finite count
+// the eight sums of a workgroup of RED_THREADS work-items: wavefront
+// butterflies (every lane adds the same two operands, in either order), then
+// the wavefronts' sums in order
+__device__ inline void red8_block(double acc[8], double* __restrict__ out) {
+    __shared__ double sh[RED_THREADS / 64][8];
+    for (int m = 32; m > 0; m >>= 1)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] += __shfl_xor(acc[k], m, 64);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sh[threadIdx.x >> 6][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        double t = 0.0;
+        for (int w = 0; w < RED_THREADS / 64; ++w) t += sh[w][threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+}
+
 __global__ __launch_bounds__(RED_THREADS) void k_frame_stats(Geo g, const float* __restrict__ X,
                                                             const float* __restrict__ valid, int use_valid,
                                                             double* __restrict__ partial) {
-    __shared__ double sh[8][RED_THREADS];
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const long N = (long)g.H * g.W;
     for (long i = (long)blockIdx.x * RED_THREADS + threadIdx.x; i < N; i += (long)gridDim.x * RED_THREADS) {
@@ -866,24 +885,20 @@ __global__ __launch_bounds__(RED_THREADS) void k_frame_stats(Geo g, const float*
         acc[6] += use_valid ? (double)valid[p] : 0.0;
         acc[7] += fin ? 0.0 : 1.0;
     }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) sh[k][threadIdx.x] = acc[k];
-    __syncthreads();
-    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-#pragma unroll
-            for (int k = 0; k < 8; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x < 8) partial[(long)blockIdx.x * 8 + threadIdx.x] = sh[threadIdx.x][0];
+    red8_block(acc, partial + (long)blockIdx.x * 8);
 }
 
-__global__ void k_frame_final(int nblocks, const double* __restrict__ partial, double* __restrict__ result) {
-    const int k = threadIdx.x;
-    if (k >= 8) return;
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += partial[(long)b * 8 + k];
-    result[k] = s;
+// one workgroup: the sum of the nb partial records, in one fixed order;
+// result[8] receives the health flag (when given) so that one copy returns both
+__global__ __launch_bounds__(RED_THREADS) void k_frame_final(int nblocks, const double* __restrict__ partial,
+                                                            double* __restrict__ result,
+                                                            const int* __restrict__ health) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += RED_THREADS)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] += partial[(long)b * 8 + k];
+    red8_block(acc, result);
+    if (health && threadIdx.x == 0) result[8] = (double)*health;
 }
 
 // output maps: inverse depth and its delta-method variance (dense H x W)
@@ -1214,8 +1229,8 @@ static const dim3 kBlock(64, 1);
 static const dim3 kBlockFused(64, 4);
 
 hipError_t launch_frame_prep(const Geo& g, const float* src, long src_pitch, float* It, float* Gx, float* Gy,
-                             hipStream_t st) {
-    hipLaunchKernelGGL(k_frame_prep, grid2d(g, kBlock), kBlock, 0, st, g, src, src_pitch, It, Gx, Gy);
+                             hipStream_t st, int* clear) {
+    hipLaunchKernelGGL(k_frame_prep, grid2d(g, kBlock), kBlock, 0, st, g, src, src_pitch, It, Gx, Gy, clear);
     return hipGetLastError();
 }
 
@@ -1289,10 +1304,10 @@ int stats_blocks(const Geo& g) {
 }
 
 hipError_t launch_frame_stats(const Geo& g, const float* X, const float* valid, int use_valid, double* partial,
-                              double* result, hipStream_t st) {
+                              double* result, hipStream_t st, const int* health) {
     const int nb = stats_blocks(g);
     hipLaunchKernelGGL(k_frame_stats, dim3(nb), dim3(RED_THREADS), 0, st, g, X, valid, use_valid, partial);
-    hipLaunchKernelGGL(k_frame_final, dim3(1), dim3(64), 0, st, nb, partial, result);
+    hipLaunchKernelGGL(k_frame_final, dim3(1), dim3(RED_THREADS), 0, st, nb, partial, result, health);
     return hipGetLastError();
 }
 

@@ -51,7 +51,6 @@ struct pixvod_ctx {
     double *partial = nullptr, *result = nullptr;
     int* health = nullptr;
     double* h_result = nullptr;
-    int* h_health = nullptr;
     bool have_kf = false, have_frame = false, has_sigma = false, have_track = false, have_var = false;
     double T_w_kf[16];
     double xi_last[6];
@@ -305,7 +304,6 @@ static void release(pixvod_ctx* c) {
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (c->h_result) (void)hipHostFree(c->h_result);
-    if (c->h_health) (void)hipHostFree(c->h_health);
     for (auto& t : c->tgraph) {
         if (t.exec) (void)hipGraphExecDestroy(t.exec);
         for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
@@ -399,10 +397,9 @@ int pixvod_create(int H, int W, const pixvod_intrinsics* K, const pixvod_params*
     if (!rc) rc = dev_alloc(c, &c->kf_stage, N * 4);
     if (!rc) rc = dev_alloc(c, &c->out_stage, N * 2);
     if (!rc) rc = dev_alloc(c, &c->partial, (size_t)nb * 8);
-    if (!rc) rc = dev_alloc(c, &c->result, 8);
+    if (!rc) rc = dev_alloc(c, &c->result, 9);
     if (!rc) rc = dev_alloc(c, &c->health, 1);
-    if (!rc && hipHostMalloc((void**)&c->h_result, 8 * sizeof(double)) != hipSuccess) rc = PIXVOD_ENOMEM;
-    if (!rc && hipHostMalloc((void**)&c->h_health, sizeof(int)) != hipSuccess) rc = PIXVOD_ENOMEM;
+    if (!rc && hipHostMalloc((void**)&c->h_result, 9 * sizeof(double)) != hipSuccess) rc = PIXVOD_ENOMEM;
     if (!rc && hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess) rc = PIXVOD_EHIP;
     if (rc) {
         std::string m = c->err.empty() ? "context allocation failed" : c->err;
@@ -646,7 +643,7 @@ static int stage_frame(pixvod_ctx* c, const float* frame, int where) {
     const float* d = nullptr;
     int rc = stage_in(c, frame, where, N, c->frame_stage, &d);
     if (rc) return rc;
-    HIP_TRY(c, launch_frame_prep(geo_of(c), d, c->W, c->It, c->Gx, c->Gy, c->stream));
+    HIP_TRY(c, launch_frame_prep(geo_of(c), d, c->W, c->It, c->Gx, c->Gy, c->stream, c->health));
     c->have_frame = true;
     return PIXVOD_OK;
 }
@@ -808,7 +805,8 @@ static int track_graph_capture(pixvod_ctx* c, pixvod_ctx::TrackGraph& t, int src
     mark();
     t.kind.push_back(PIXVOD_PROF_FUSED_FINAL);
     t.launches.push_back(1);
-    if (le == hipSuccess) le = launch_frame_stats(g, c->X[cur], c->valid, 1, c->partial, c->result, c->stream);
+    if (le == hipSuccess)
+        le = launch_frame_stats(g, c->X[cur], c->valid, 1, c->partial, c->result, c->stream, c->health);
     hipGraph_t gr = nullptr;
     const hipError_t ce = hipStreamEndCapture(c->stream, &gr);
     if (le != hipSuccess || ce != hipSuccess) {
@@ -884,7 +882,7 @@ int pixvod_track(pixvod_ctx* c, const float* frame, int where, int n_iters, pixv
         if (rc) return rc;
     }
     if (!graphed) {
-        HIP_TRY(c, hipMemsetAsync(c->health, 0, sizeof(int), c->stream));
+        // the health flag was cleared by the frame preparation of stage_frame
         if (n_iters == 0) {
             HIP_TRY(c, launch_valid_only(g, strengths_of(c), inputs_of(c), c->X[c->cur], c->valid, c->stream));
             c->have_var = false;
@@ -892,7 +890,7 @@ int pixvod_track(pixvod_ctx* c, const float* frame, int where, int n_iters, pixv
             rc = run_iterations(c, n_iters);
             if (rc) return rc;
         }
-        HIP_TRY(c, launch_frame_stats(g, c->X[c->cur], c->valid, 1, c->partial, c->result, c->stream));
+        HIP_TRY(c, launch_frame_stats(g, c->X[c->cur], c->valid, 1, c->partial, c->result, c->stream, c->health));
     }
     if (out->inv_depth || out->inv_depth_var) {
         float* d_inv = out->inv_depth;
@@ -911,8 +909,7 @@ int pixvod_track(pixvod_ctx* c, const float* frame, int where, int n_iters, pixv
                                           hipMemcpyDeviceToHost, c->stream));
         }
     }
-    HIP_TRY(c, hipMemcpyAsync(c->h_result, c->result, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(c->h_health, c->health, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->h_result, c->result, 9 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (!c->pending.empty() || !c->graph_pending.empty()) prof_collect(c);
 
@@ -933,7 +930,7 @@ int pixvod_track(pixvod_ctx* c, const float* frame, int where, int n_iters, pixv
     unsigned f = 0;
     if (c->frames_since_kf >= c->P.kf_max_frames || vf < c->P.kf_min_valid_frac) f |= PIXVOD_KEYFRAME_DUE;
     if (vf < c->P.kf_min_valid_frac) f |= PIXVOD_LOW_OVERLAP;
-    if (c->h_result[7] > 0.0 || *c->h_health != 0) f |= PIXVOD_DIVERGED;
+    if (c->h_result[7] > 0.0 || c->h_result[8] != 0.0) f |= PIXVOD_DIVERGED;
     out->flags = f;
     return PIXVOD_OK;
 }

@@ -388,57 +388,81 @@ __global__ __launch_bounds__(kTreeThreads) void k_tr_node(Geo g, TreeGeo t, Stre
     const int x = i % lv.W, y = i / lv.W;
     const long n = (long)lv.off + i;
     double tau[6], R[9], tt[3], L[21], eta[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) tau[k] = (double)NX[(long)(TN_TAU + k) * t.nplane + n];
-    se3_exp(tau, R, tt);
-    node_prior(s, lv.lamP, tau, R, tt, L, eta);
     float msg[5][27];
     bool ok = true;
     if (PROLOGUE) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) tau[k] = (double)NX[(long)(TN_TAU + k) * t.nplane + n];
+        se3_exp(tau, R, tt);
+        node_prior(s, lv.lamP, tau, R, tt, L, eta);
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
             load_part27(NX + (long)(TN_UP + 27 * k) * t.nplane, t.nplane, n, msg[k]);
             add_identity<6>(msg[k], L, eta);
         }
     } else {
-        // parent's partial for this child slot
+        // --- every load issued before any use (its address depends only on
+        // the node index): the node's pose, the parent's pose and its partial
+        // for this child slot, the children's poses and partials towards this
+        // node. A missing parent or child reads the node itself; its values
+        // are discarded.
+        float tnf[6], tpf[6], tcf[4][6];
+        const bool has_par = lv.l < t.L;
+        const long pp = has_par ? (long)lv.offp + (long)(y >> 1) * lv.Wp + (x >> 1) : n;
+        const int qn = ((y & 1) << 1) | (x & 1);
+        bool has_c[4];
 #pragma unroll
-        for (int k = 0; k < 27; ++k) msg[0][k] = 0.0f;
-        if (lv.l < t.L) {
-            const long pp = (long)lv.offp + (long)(y >> 1) * lv.Wp + (x >> 1);
-            const int qn = ((y & 1) << 1) | (x & 1);
+        for (int k = 0; k < 6; ++k) tnf[k] = NX[(long)(TN_TAU + k) * t.nplane + n];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) tpf[k] = NX[(long)(TN_TAU + k) * t.nplane + pp];
+        load_part27(NX + (long)(TN_CH + 27 * qn) * t.nplane, t.nplane, pp, msg[0]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int cx = 2 * x + (q & 1), cy = 2 * y + (q >> 1);
+            has_c[q] = cx < lv.Wc && cy < lv.Hc;
+            const int cxc = has_c[q] ? cx : 2 * x, cyc = has_c[q] ? cy : 2 * y;
+            if (lv.l == 1) {
+                const long pc = pix_of(g, cxc, cyc);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) tcf[q][k] = X[(long)(P_TAU + k) * g.plane + pc];
+                load_part27(X + (long)TP_UP * g.plane, g.plane, pc, msg[1 + q]);
+            } else {
+                const long nc = (long)lv.offc + (long)cyc * lv.Wc + cxc;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) tcf[q][k] = NX[(long)(TN_TAU + k) * t.nplane + nc];
+                load_part27(NX + (long)TN_UP * t.nplane, t.nplane, nc, msg[1 + q]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) tau[k] = (double)tnf[k];
+        se3_exp(tau, R, tt);
+        node_prior(s, lv.lamP, tau, R, tt, L, eta);
+        // parent's partial for this child slot, completed in place
+        if (has_par) {
             double tp[6], Rp[9], trp[3], r[6];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) tp[k] = (double)NX[(long)(TN_TAU + k) * t.nplane + pp];
+            for (int k = 0; k < 6; ++k) tp[k] = (double)tpf[k];
             se3_exp(tp, Rp, trp);
             se3_between(Rp, trp, R, tt, r);
-            float part[27];
-            load_part27(NX + (long)(TN_CH + 27 * qn) * t.nplane, t.nplane, pp, part);
-            complete_identity<6>(part, r, L, eta, msg[0]);
+            complete_identity<6>(msg[0], r, L, eta, msg[0]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 27; ++k) msg[0][k] = 0.0f;
         }
         // children's partials towards this node
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
+            if (!has_c[q]) {
 #pragma unroll
-            for (int k = 0; k < 27; ++k) msg[1 + q][k] = 0.0f;
-            const int cx = 2 * x + (q & 1), cy = 2 * y + (q >> 1);
-            if (cx >= lv.Wc || cy >= lv.Hc) continue;
-            double tc[6], Rc[9], trc[3], r[6];
-            float part[27];
-            if (lv.l == 1) {
-                const long pc = pix_of(g, cx, cy);
-#pragma unroll
-                for (int k = 0; k < 6; ++k) tc[k] = (double)X[(long)(P_TAU + k) * g.plane + pc];
-                load_part27(X + (long)TP_UP * g.plane, g.plane, pc, part);
-            } else {
-                const long nc = (long)lv.offc + (long)cy * lv.Wc + cx;
-#pragma unroll
-                for (int k = 0; k < 6; ++k) tc[k] = (double)NX[(long)(TN_TAU + k) * t.nplane + nc];
-                load_part27(NX + (long)TN_UP * t.nplane, t.nplane, nc, part);
+                for (int k = 0; k < 27; ++k) msg[1 + q][k] = 0.0f;
+                continue;
             }
+            double tc[6], Rc[9], trc[3], r[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) tc[k] = (double)tcf[q][k];
             se3_exp(tc, Rc, trc);
             se3_between(Rc, trc, R, tt, r);
-            complete_identity<6>(part, r, L, eta, msg[1 + q]);
+            complete_identity<6>(msg[1 + q], r, L, eta, msg[1 + q]);
         }
         // update: mean, relinearisation, transport
         double idg[6], m[6];

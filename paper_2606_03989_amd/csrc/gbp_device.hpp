@@ -409,22 +409,6 @@ __device__ inline float plane_at(const float* p, const Geo& g, int u, int v) {
     return p[(long)v * g.pitch + u];
 }
 
-// bilinear samples of I_t, G_x, G_y at (x, y) in [0, W-1] x [0, H-1]
-__device__ inline void sample3(const Inputs& in, const Geo& g, double x, double y, double& I,
-                               double& gx, double& gy) {
-    int x0 = (int)floor(x), y0 = (int)floor(y);
-    x0 = x0 > g.W - 2 ? g.W - 2 : (x0 < 0 ? 0 : x0);
-    y0 = y0 > g.H - 2 ? g.H - 2 : (y0 < 0 ? 0 : y0);
-    const double fx = x - x0, fy = y - y0;
-    const long o = (long)y0 * g.pitch + x0;
-    const long o2 = o + g.pitch;
-    const double w00 = (1.0 - fx) * (1.0 - fy), w10 = fx * (1.0 - fy), w01 = (1.0 - fx) * fy, w11 = fx * fy;
-    I = (1.0 - fy) * ((1.0 - fx) * in.It[o] + fx * in.It[o + 1]) + fy * ((1.0 - fx) * in.It[o2] + fx * in.It[o2 + 1]);
-    gx = (1.0 - fy) * ((1.0 - fx) * in.Gx[o] + fx * in.Gx[o + 1]) + fy * ((1.0 - fx) * in.Gx[o2] + fx * in.Gx[o2 + 1]);
-    gy = (1.0 - fy) * ((1.0 - fx) * in.Gy[o] + fx * in.Gy[o + 1]) + fy * ((1.0 - fx) * in.Gy[o2] + fx * in.Gy[o2 + 1]);
-    (void)w00; (void)w10; (void)w01; (void)w11;
-}
-
 constexpr double WARP_EPS = 1e-3;
 
 // per-pixel inputs of the unary factors: keyframe intensity, photometric sigma
@@ -453,55 +437,93 @@ struct Photo {
     bool valid;
 };
 
-__device__ inline Photo photometric(const Geo& g, const Strengths& s, const Inputs& in, int u, int v,
-                                    const double R[9], const double t[3], double ell, const PixelInputs& pin) {
+// The factor in two halves, so that a caller can put independent work
+// between the sample loads and their use: photometric_begin computes the
+// warp and issues the twelve bilinear-sample loads (at clamped addresses,
+// also for an invalid warp, whose values are then unused), photometric_end
+// forms the factor. photometric() is the two in a row.
+struct PhotoPre {
+    double q0, q1, rho, a0, a1, iz, fx, fy;
+    float s[12];           // I_t, G_x, G_y at the four corners (o, o + 1, o + pitch, o + pitch + 1)
+    bool valid;
+};
+
+__device__ inline PhotoPre photometric_begin(const Geo& g, const Inputs& in, int u, int v, const double R[9],
+                                             const double t[3], double ell) {
+    PhotoPre p;
+    p.q0 = ((double)u - g.cx) / g.fx;
+    p.q1 = ((double)v - g.cy) / g.fy;
+    p.rho = exp(-ell);
+    p.a0 = R[0] * p.q0 + R[1] * p.q1 + R[2] + p.rho * t[0];
+    p.a1 = R[3] * p.q0 + R[4] * p.q1 + R[5] + p.rho * t[1];
+    const double a2 = R[6] * p.q0 + R[7] * p.q1 + R[8] + p.rho * t[2];
+    p.iz = rcp_nr(a2 > 0.0 ? a2 : 1.0);
+    const double wx = g.fx * p.a0 * p.iz + g.cx, wy = g.fy * p.a1 * p.iz + g.cy;
+    p.valid = a2 > 0.0 && wx >= -WARP_EPS && wx <= (g.W - 1) + WARP_EPS && wy >= -WARP_EPS &&
+              wy <= (g.H - 1) + WARP_EPS;
+    const double x = p.valid ? fmin(fmax(wx, 0.0), (double)(g.W - 1)) : 0.0;
+    const double y = p.valid ? fmin(fmax(wy, 0.0), (double)(g.H - 1)) : 0.0;
+    int x0 = (int)floor(x), y0 = (int)floor(y);
+    x0 = x0 > g.W - 2 ? g.W - 2 : (x0 < 0 ? 0 : x0);
+    y0 = y0 > g.H - 2 ? g.H - 2 : (y0 < 0 ? 0 : y0);
+    p.fx = x - x0;
+    p.fy = y - y0;
+    const long o = (long)y0 * g.pitch + x0;
+    const long o2 = o + g.pitch;
+    const long off[4] = {o, o + 1, o2, o2 + 1};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        p.s[c] = in.It[off[c]];
+        p.s[4 + c] = in.Gx[off[c]];
+        p.s[8 + c] = in.Gy[off[c]];
+    }
+    return p;
+}
+
+__device__ inline Photo photometric_end(const PhotoPre& p, const Geo& g, const Strengths& s, const double R[9],
+                                        const double t[3], const PixelInputs& pin) {
     Photo f;
     f.valid = false;
     f.w = 0.0;
     f.r = 0.0;
 #pragma unroll
     for (int a = 0; a < 7; ++a) f.J[a] = 0.0;
-    const double q0 = ((double)u - g.cx) / g.fx, q1 = ((double)v - g.cy) / g.fy;
-    const double rho = exp(-ell);
-    const double a0 = R[0] * q0 + R[1] * q1 + R[2] + rho * t[0];
-    const double a1 = R[3] * q0 + R[4] * q1 + R[5] + rho * t[1];
-    const double a2 = R[6] * q0 + R[7] * q1 + R[8] + rho * t[2];
-    if (a2 > 0.0) {
-        const double iz = rcp_nr(a2);
-        const double wx = g.fx * a0 * iz + g.cx, wy = g.fy * a1 * iz + g.cy;
-        if (wx >= -WARP_EPS && wx <= (g.W - 1) + WARP_EPS && wy >= -WARP_EPS && wy <= (g.H - 1) + WARP_EPS) {
-            f.valid = true;
-            const double x = fmin(fmax(wx, 0.0), (double)(g.W - 1));
-            const double y = fmin(fmax(wy, 0.0), (double)(g.H - 1));
-            double It, gx, gy;
-            sample3(in, g, x, y, It, gx, gy);
-            f.r = (double)pin.Is - It;
-            // c = -g^T dw/da  (row 3-vector)
-            const double c0 = -gx * g.fx * iz, c1 = -gy * g.fy * iz;
-            const double c2 = (gx * g.fx * a0 + gy * g.fy * a1) * iz * iz;
-            // J_theta = c.(-R [q]x d) = -(R^T c).(q x d) = -((R^T c) x q).d with b = R^T c
-            const double b0 = R[0] * c0 + R[3] * c1 + R[6] * c2;
-            const double b1 = R[1] * c0 + R[4] * c1 + R[7] * c2;
-            const double b2 = R[2] * c0 + R[5] * c1 + R[8] * c2;
-            f.J[0] = -(b1 * 1.0 - b2 * q1);
-            f.J[1] = -(b2 * q0 - b0 * 1.0);
-            f.J[2] = -(b0 * q1 - b1 * q0);
-            f.J[3] = rho * b0;
-            f.J[4] = rho * b1;
-            f.J[5] = rho * b2;
-            f.J[6] = -rho * (c0 * t[0] + c1 * t[1] + c2 * t[2]);
-            const double isig = s.has_sigma_map ? rcp_nr((double)pin.sigD) : s.inv_sigD;
-            const double lamD = isig * isig;
-            const double M = fabs(f.r) * isig;
-            double kappa = 1.0;
-            if (M > s.huber_k) {
-                const double iM = rcp_nr(M);
-                kappa = s.huber_k * iM * (2.0 - s.huber_k * iM);
-            }
-            f.w = kappa * lamD;
-        }
+    if (!p.valid) return f;
+    f.valid = true;
+    const double fx = p.fx, fy = p.fy, iz = p.iz, rho = p.rho, q0 = p.q0, q1 = p.q1;
+    const double It = (1.0 - fy) * ((1.0 - fx) * p.s[0] + fx * p.s[1]) + fy * ((1.0 - fx) * p.s[2] + fx * p.s[3]);
+    const double gx = (1.0 - fy) * ((1.0 - fx) * p.s[4] + fx * p.s[5]) + fy * ((1.0 - fx) * p.s[6] + fx * p.s[7]);
+    const double gy = (1.0 - fy) * ((1.0 - fx) * p.s[8] + fx * p.s[9]) + fy * ((1.0 - fx) * p.s[10] + fx * p.s[11]);
+    f.r = (double)pin.Is - It;
+    // c = -g^T dw/da  (row 3-vector)
+    const double c0 = -gx * g.fx * iz, c1 = -gy * g.fy * iz;
+    const double c2 = (gx * g.fx * p.a0 + gy * g.fy * p.a1) * iz * iz;
+    // J_theta = c.(-R [q]x d) = -(R^T c).(q x d) = -((R^T c) x q).d with b = R^T c
+    const double b0 = R[0] * c0 + R[3] * c1 + R[6] * c2;
+    const double b1 = R[1] * c0 + R[4] * c1 + R[7] * c2;
+    const double b2 = R[2] * c0 + R[5] * c1 + R[8] * c2;
+    f.J[0] = -(b1 * 1.0 - b2 * q1);
+    f.J[1] = -(b2 * q0 - b0 * 1.0);
+    f.J[2] = -(b0 * q1 - b1 * q0);
+    f.J[3] = rho * b0;
+    f.J[4] = rho * b1;
+    f.J[5] = rho * b2;
+    f.J[6] = -rho * (c0 * t[0] + c1 * t[1] + c2 * t[2]);
+    const double isig = s.has_sigma_map ? rcp_nr((double)pin.sigD) : s.inv_sigD;
+    const double lamD = isig * isig;
+    const double M = fabs(f.r) * isig;
+    double kappa = 1.0;
+    if (M > s.huber_k) {
+        const double iM = rcp_nr(M);
+        kappa = s.huber_k * iM * (2.0 - s.huber_k * iM);
     }
+    f.w = kappa * lamD;
     return f;
+}
+
+__device__ inline Photo photometric(const Geo& g, const Strengths& s, const Inputs& in, int u, int v,
+                                    const double R[9], const double t[3], double ell, const PixelInputs& pin) {
+    return photometric_end(photometric_begin(g, in, u, v, R, t, ell), g, s, R, t, pin);
 }
 
 // L += w J^T J, eta -= w J r for a valid photometric factor

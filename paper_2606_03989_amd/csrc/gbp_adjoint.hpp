@@ -185,30 +185,47 @@ __device__ inline void unary_adjoint(const Geo& g, const Strengths& s, const Inp
     const double a0 = R[0] * q0 + R[1] * q1 + R[2] + rho * t[0];
     const double a1 = R[3] * q0 + R[4] * q1 + R[5] + rho * t[1];
     const double a2 = R[6] * q0 + R[7] * q1 + R[8] + rho * t[2];
-    if (a2 > 0.0) {
-        const double iz = rcp_nr(a2);
-        const double wx = g.fx * a0 * iz + g.cx, wy = g.fy * a1 * iz + g.cy;
-        if (wx >= -WARP_EPS && wx <= (g.W - 1) + WARP_EPS && wy >= -WARP_EPS && wy <= (g.H - 1) + WARP_EPS) {
-            const double x = fmin(fmax(wx, 0.0), (double)(g.W - 1));
-            const double y = fmin(fmax(wy, 0.0), (double)(g.H - 1));
+    // the warp, its validity and the samples' loads, outside the validity
+    // branches (clamped addresses; an invalid warp's values are unused) so
+    // that the loads are not held back by them
+    const double iz = rcp_nr(a2 > 0.0 ? a2 : 1.0);
+    const double wx = g.fx * a0 * iz + g.cx, wy = g.fy * a1 * iz + g.cy;
+    const bool warp_ok = a2 > 0.0 && wx >= -WARP_EPS && wx <= (g.W - 1) + WARP_EPS && wy >= -WARP_EPS &&
+                         wy <= (g.H - 1) + WARP_EPS;
+    const double x = warp_ok ? fmin(fmax(wx, 0.0), (double)(g.W - 1)) : 0.0;
+    const double y = warp_ok ? fmin(fmax(wy, 0.0), (double)(g.H - 1)) : 0.0;
+    int x0 = (int)floor(x), y0 = (int)floor(y);
+    x0 = x0 > g.W - 2 ? g.W - 2 : (x0 < 0 ? 0 : x0);
+    y0 = y0 > g.H - 2 ? g.H - 2 : (y0 < 0 ? 0 : y0);
+    const long o = (long)y0 * g.pitch + x0, o2 = o + g.pitch;
+    const long pix = (long)v * g.pitch + u;
+    float smp[3][4];
+    {
+        const float* planes[3] = {in.It, in.Gx, in.Gy};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            smp[k][0] = planes[k][o];
+            smp[k][1] = planes[k][o + 1];
+            smp[k][2] = planes[k][o2];
+            smp[k][3] = planes[k][o2 + 1];
+        }
+    }
+    const float Isv = in.Is[pix];
+    const float sigv = s.has_sigma_map ? in.sigD[pix] : 1.0f;
+    if (warp_ok) {
+        {
             // bilinear samples and their in-cell derivatives
-            int x0 = (int)floor(x), y0 = (int)floor(y);
-            x0 = x0 > g.W - 2 ? g.W - 2 : (x0 < 0 ? 0 : x0);
-            y0 = y0 > g.H - 2 ? g.H - 2 : (y0 < 0 ? 0 : y0);
             const double fx = x - x0, fy = y - y0;
-            const long o = (long)y0 * g.pitch + x0, o2 = o + g.pitch;
             double val[3], dx[3], dy[3];
-            const float* planes[3] = {in.It, in.Gx, in.Gy};
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                const double c00 = planes[k][o], c10 = planes[k][o + 1], c01 = planes[k][o2], c11 = planes[k][o2 + 1];
+                const double c00 = smp[k][0], c10 = smp[k][1], c01 = smp[k][2], c11 = smp[k][3];
                 val[k] = (1.0 - fy) * ((1.0 - fx) * c00 + fx * c10) + fy * ((1.0 - fx) * c01 + fx * c11);
                 dx[k] = (1.0 - fy) * (c10 - c00) + fy * (c11 - c01);
                 dy[k] = (1.0 - fx) * (c01 - c00) + fx * (c11 - c10);
             }
             const double gx = val[1], gy = val[2];
-            const long pix = (long)v * g.pitch + u;
-            const double r = (double)in.Is[pix] - val[0];
+            const double r = (double)Isv - val[0];
             const double c[3] = {-gx * g.fx * iz, -gy * g.fy * iz, (gx * g.fx * a0 + gy * g.fy * a1) * iz * iz};
             double b[3];
 #pragma unroll
@@ -220,7 +237,7 @@ __device__ inline void unary_adjoint(const Geo& g, const Strengths& s, const Inp
             J[5] = rho * b[2];
             const double ct = c[0] * t[0] + c[1] * t[1] + c[2] * t[2];
             J[6] = -rho * ct;
-            const double isig = s.has_sigma_map ? rcp_nr((double)in.sigD[pix]) : s.inv_sigD;
+            const double isig = s.has_sigma_map ? rcp_nr((double)sigv) : s.inv_sigD;
             const double lamD = isig * isig;
             const double M = fabs(r) * isig;
             double kappa = 1.0;

@@ -88,7 +88,7 @@ struct SeqDesc {
     int tile_base;        // natural index of the sequence's first work item
     int tiles_x;          // tiles per image row
     int n_tiles;
-    int pad;
+    int stat_base;        // first of the sequence's statistics records (one per 64 x 4 tile)
 };
 
 // arguments of the batched launches
@@ -101,7 +101,8 @@ struct BatchLaunch {
     int parity;           // buffer holding the canonical state
     Strengths s;
     int* health;
-    double* partial;      // 8 doubles per work item
+    double* partial;      // 8 doubles per 64 x 4 statistics tile of every sequence
+    int max_stat_tiles;   // statistics tiles of the largest image
     double* result;       // 8 doubles per sequence
     // keyframe test and re-anchoring on the device (Sec. 3.5)
     int* fsk;             // per sequence: frames tracked since its keyframe

@@ -32,6 +32,7 @@ hipError_t launch_fu_step_tape(const Geo& g, const Strengths& s, const Inputs& i
                                int* health, hipStream_t st);
 hipError_t launch_valid_only(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* valid,
                              hipStream_t st);
+// statistics records of an image: one per 64 x 4 pixel tile
 int stats_blocks(const Geo& g);
 // result (9 doubles): the six pose sums, valid count, non-finite count, and
 // the health flag *health when given

@@ -866,38 +866,61 @@ __device__ inline void red8_block(double acc[8], double* __restrict__ out) {
     }
 }
 
-__global__ __launch_bounds__(RED_THREADS) void k_frame_stats(Geo g, const float* __restrict__ X,
-                                                            const float* __restrict__ valid, int use_valid,
-                                                            double* __restrict__ partial) {
+// The sums are taken over a fixed decomposition of the image, independent of
+// any launch shape: 64 x 4 pixel tiles in row-major tile order, one record per
+// tile, then the records of an image in one strided order. A single context and
+// a batch therefore reduce a sequence's planes in the same order and agree bit
+// for bit.
+constexpr int ST_X = 64, ST_Y = RED_THREADS / ST_X;
+
+__host__ __device__ inline int stat_tiles_x(int W) { return (W + ST_X - 1) / ST_X; }
+__host__ __device__ inline int stat_tiles(int H, int W) { return stat_tiles_x(W) * ((H + ST_Y - 1) / ST_Y); }
+
+// one 64 x 4 tile: sum of the six pose planes, valid count (when use_valid),
+// non-finite count, written as out[0..7]; one workgroup of RED_THREADS
+__device__ inline void tile_stats(const Geo& g, const float* __restrict__ X, const float* __restrict__ valid,
+                                  int use_valid, int tile, double* __restrict__ out) {
+    const int ntx = stat_tiles_x(g.W);
+    const int u = (tile % ntx) * ST_X + (int)(threadIdx.x % ST_X);
+    const int v = (tile / ntx) * ST_Y + (int)(threadIdx.x / ST_X);
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const long N = (long)g.H * g.W;
-    for (long i = (long)blockIdx.x * RED_THREADS + threadIdx.x; i < N; i += (long)gridDim.x * RED_THREADS) {
-        const int u = (int)(i % g.W), v = (int)(i / g.W);
+    if (u < g.W && v < g.H) {
         const long p = pix_of(g, u, v);
         bool fin = true;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             const float x = X[(long)k * g.plane + p];
-            acc[k] += (double)x;
+            acc[k] = (double)x;
             fin = fin && isfinite(x);
         }
         fin = fin && isfinite(X[(long)P_ELL * g.plane + p]);
-        acc[6] += use_valid ? (double)valid[p] : 0.0;
-        acc[7] += fin ? 0.0 : 1.0;
+        acc[6] = use_valid ? (double)valid[p] : 0.0;
+        acc[7] = fin ? 0.0 : 1.0;
     }
-    red8_block(acc, partial + (long)blockIdx.x * 8);
+    red8_block(acc, out);
 }
 
-// one workgroup: the sum of the nb partial records, in one fixed order;
+// the n tile records of one image, strided over the workgroup, then reduced
+__device__ inline void image_stats(const double* __restrict__ partial, int n, double* __restrict__ out) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < n; b += RED_THREADS)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] += partial[(long)b * 8 + k];
+    red8_block(acc, out);
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_frame_stats(Geo g, const float* __restrict__ X,
+                                                            const float* __restrict__ valid, int use_valid,
+                                                            double* __restrict__ partial) {
+    tile_stats(g, X, valid, use_valid, blockIdx.x, partial + (long)blockIdx.x * 8);
+}
+
+// one workgroup: the sum of the nb tile records, in one fixed order;
 // result[8] receives the health flag (when given) so that one copy returns both
 __global__ __launch_bounds__(RED_THREADS) void k_frame_final(int nblocks, const double* __restrict__ partial,
                                                             double* __restrict__ result,
                                                             const int* __restrict__ health) {
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < nblocks; b += RED_THREADS)
-#pragma unroll
-        for (int k = 0; k < 8; ++k) acc[k] += partial[(long)b * 8 + k];
-    red8_block(acc, result);
+    image_stats(partial, nblocks, result);
     if (health && threadIdx.x == 0) result[8] = (double)*health;
 }
 
@@ -992,66 +1015,29 @@ __global__ __launch_bounds__(256) void k_batch_iterate(const SeqDesc* __restrict
     iterate_pixel_pf<FINAL, false>(d->g, s, d->in, X, Y, d->var_ll, d->valid, health, u, v);
 }
 
-// per work item: sum of the six pose planes, valid count, non-finite count of
-// the tile, written at the item's natural index (fixed-order reduction)
-__global__ __launch_bounds__(256) void k_batch_stats(const SeqDesc* __restrict__ seqs, const int2* __restrict__ work,
-                                                     int parity, double* __restrict__ partial) {
-    __shared__ double sh[8][256];
-    const SeqDesc* d;
-    int u, v, item;
-    const bool in_img = batch_pixel(seqs, work, d, u, v, item);
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (in_img) {
-        const float* X = parity ? d->X1 : d->X0;
-        const long p = pix_of(d->g, u, v);
-        bool fin = true;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            const float x = X[(long)k * d->g.plane + p];
-            acc[k] = (double)x;
-            fin = fin && isfinite(x);
-        }
-        fin = fin && isfinite(X[(long)P_ELL * d->g.plane + p]);
-        acc[6] = (double)d->valid[p];
-        acc[7] = fin ? 0.0 : 1.0;
-    }
-    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
-    const int nt = blockDim.x * blockDim.y;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) sh[k][tid] = acc[k];
-    for (int k = nt; k < 256; k += nt)
-        if (tid + k < 256)
-#pragma unroll
-            for (int c = 0; c < 8; ++c) sh[c][tid + k] = 0.0;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (tid < w)
-#pragma unroll
-            for (int k = 0; k < 8; ++k) sh[k][tid] += sh[k][tid + w];
-        __syncthreads();
-    }
-    if (tid < 8) partial[(long)item * 8 + tid] = sh[tid][0];
+// per sequence (blockIdx.y) and 64 x 4 tile of its image (blockIdx.x): the
+// tile's sums, at the sequence's record base; the same tiles and order as a
+// single context's statistics
+__global__ __launch_bounds__(RED_THREADS) void k_batch_stats(const SeqDesc* __restrict__ seqs, int parity,
+                                                            double* __restrict__ partial) {
+    const SeqDesc* d = &seqs[blockIdx.y];
+    if ((int)blockIdx.x >= stat_tiles(d->g.H, d->g.W)) return;
+    const float* X = parity ? d->X1 : d->X0;
+    tile_stats(d->g, X, d->valid, 1, blockIdx.x, partial + (long)(d->stat_base + (int)blockIdx.x) * 8);
 }
 
-// one block per sequence: sums its tiles' partials in order
-__global__ __launch_bounds__(256) void k_batch_final(const SeqDesc* __restrict__ seqs, const double* __restrict__ partial,
-                                                     double* __restrict__ result) {
-    __shared__ double sh[8][256];
-    const SeqDesc& d = seqs[blockIdx.x];
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int t = threadIdx.x; t < d.n_tiles; t += 256)
-#pragma unroll
-        for (int k = 0; k < 8; ++k) acc[k] += partial[(long)(d.tile_base + t) * 8 + k];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) sh[k][threadIdx.x] = acc[k];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-#pragma unroll
-            for (int k = 0; k < 8; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x < 8) result[(long)blockIdx.x * 8 + threadIdx.x] = sh[threadIdx.x][0];
+// one workgroup per sequence: its tile records in the single-context order
+__global__ __launch_bounds__(RED_THREADS) void k_batch_final(const SeqDesc* __restrict__ seqs,
+                                                            const double* __restrict__ partial,
+                                                            double* __restrict__ result) {
+    const SeqDesc* d = &seqs[blockIdx.x];
+    image_stats(partial + (long)d->stat_base * 8, stat_tiles(d->g.H, d->g.W), result + (long)blockIdx.x * 8);
+}
+
+static void launch_batch_stats(const BatchLaunch& b, int parity, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_stats, dim3(b.max_stat_tiles, b.n_seq), dim3(RED_THREADS), 0, st, b.seqs, parity,
+                       b.partial);
+    hipLaunchKernelGGL(k_batch_final, dim3(b.n_seq), dim3(RED_THREADS), 0, st, b.seqs, b.partial, b.result);
 }
 
 __global__ void k_clear_int(int* __restrict__ p) {
@@ -1144,8 +1130,7 @@ hipError_t launch_batch_frame_step(const BatchLaunch& b, int n_iters, hipStream_
             parity ^= 1;
         }
     }
-    hipLaunchKernelGGL(k_batch_stats, grid, blk, 0, st, b.seqs, b.work, parity, b.partial);
-    hipLaunchKernelGGL(k_batch_final, dim3(b.n_seq), dim3(256), 0, st, b.seqs, b.partial, b.result);
+    launch_batch_stats(b, parity, st);
     return launch_batch_keyframe(b, parity, st);
 }
 
@@ -1196,8 +1181,7 @@ hipError_t launch_batch_frame_step_persistent(const BatchLaunch& b, int n_iters,
     const int fin = b.parity ^ 1 ^ (n_passes & 1);
     hipLaunchKernelGGL(k_batch_iterate<true>, grid, blk, 0, st, b.seqs, b.work, fin, b.s, b.health);
     const int par = fin ^ 1;
-    hipLaunchKernelGGL(k_batch_stats, grid, blk, 0, st, b.seqs, b.work, par, b.partial);
-    hipLaunchKernelGGL(k_batch_final, dim3(b.n_seq), dim3(256), 0, st, b.seqs, b.partial, b.result);
+    launch_batch_stats(b, par, st);
     return launch_batch_keyframe(b, par, st);
 }
 
@@ -1295,13 +1279,7 @@ hipError_t launch_valid_only(const Geo& g, const Strengths& s, const Inputs& in,
     return hipGetLastError();
 }
 
-int stats_blocks(const Geo& g) {
-    const long N = (long)g.H * g.W;
-    long b = (N + RED_THREADS * 8 - 1) / (RED_THREADS * 8);
-    if (b < 1) b = 1;
-    if (b > 1024) b = 1024;
-    return (int)b;
-}
+int stats_blocks(const Geo& g) { return stat_tiles(g.H, g.W); }
 
 hipError_t launch_frame_stats(const Geo& g, const float* X, const float* valid, int use_valid, double* partial,
                               double* result, hipStream_t st, const int* health) {

@@ -1074,6 +1074,7 @@ struct pixvod_batch {
     SeqDesc* d_seqs = nullptr;
     int2* d_work = nullptr;
     int n_work = 0, tile_x = 64, tile_y = 4;
+    int max_stat_tiles = 0;  // 64 x 4 statistics tiles of the largest image
     double *d_partial = nullptr, *d_result = nullptr, *h_result = nullptr;
     int *d_health = nullptr, *h_health = nullptr;
     int parity = 0;
@@ -1161,7 +1162,7 @@ static void batch_release(pixvod_batch* b) {
 // workgroups dispatched to one XCD (w mod 8) cover a contiguous range
 static int batch_build_work(pixvod_batch* b) {
     std::vector<SeqDesc> descs(b->n);
-    int total = 0;
+    int total = 0, n_stat = 0, max_stat = 0;
     for (int i = 0; i < b->n; ++i) {
         BatchSeq& q = b->seq[i];
         SeqDesc& d = descs[i];
@@ -1191,6 +1192,10 @@ static int batch_build_work(pixvod_batch* b) {
         d.n_tiles = d.tiles_x * ty;
         d.tile_base = total;
         total += d.n_tiles;
+        const int nst = stats_blocks(d.g);
+        d.stat_base = n_stat;
+        n_stat += nst;
+        if (nst > max_stat) max_stat = nst;
     }
     std::vector<int2> natural(total);
     for (int i = 0; i < b->n; ++i)
@@ -1205,12 +1210,13 @@ static int batch_build_work(pixvod_batch* b) {
     b->d_work = nullptr;
     b->d_partial = nullptr;
     if (hipMalloc((void**)&b->d_work, sizeof(int2) * total) != hipSuccess ||
-        hipMalloc((void**)&b->d_partial, sizeof(double) * 8 * total) != hipSuccess)
+        hipMalloc((void**)&b->d_partial, sizeof(double) * 8 * n_stat) != hipSuccess)
         return bfail(b, PIXVOD_ENOMEM, "work list allocation failed");
     HIP_TRY_B(b, hipMemcpy(b->d_work, work.data(), sizeof(int2) * total, hipMemcpyHostToDevice));
     HIP_TRY_B(b, hipMemcpy(b->d_seqs, descs.data(), sizeof(SeqDesc) * b->n, hipMemcpyHostToDevice));
     b->descs = descs;
     b->n_work = total;
+    b->max_stat_tiles = max_stat;
     b->persistent_grid = 0;
     batch_drop_graphs(b);
     return PIXVOD_OK;
@@ -1228,6 +1234,7 @@ static BatchLaunch batch_launch_args(const pixvod_batch* b) {
     L.s = strengths_of_params(b->P);
     L.health = b->d_health;
     L.partial = b->d_partial;
+    L.max_stat_tiles = b->max_stat_tiles;
     L.result = b->d_result;
     L.fsk = b->d_fsk;
     L.flags = b->d_flags;

@@ -104,9 +104,9 @@ def test_batch_equals_per_sequence_contexts():
         for i, (s, t) in enumerate(zip(seqs, singles)):
             rs = t.track(s["frames"][f], 6)
             np.testing.assert_array_equal(b.get_state(i), t.get_state())
-            # the pose mean is reduced per tile in the batch and per strided
-            # block in a single context: equal up to summation order
-            np.testing.assert_allclose(rb[i]["xi"], rs["xi"], rtol=1e-13, atol=1e-18)
+            # both reduce the pose planes over the same 64 x 4 tiles in the
+            # same order, so the pose means agree bit for bit
+            np.testing.assert_array_equal(rb[i]["xi"], rs["xi"])
             np.testing.assert_array_equal(rb[i]["inv_depth"], rs["inv_depth"])
             assert rb[i]["frames_since_keyframe"] == rs["frames_since_keyframe"] == f + 1
             assert rb[i]["flags"] == rs["flags"]
@@ -184,7 +184,7 @@ def test_full_size_mixed_batch_sampled_against_per_sequence():
         t = pv.Tracker(H, W, _K(Ks[s]), **PARAMS)
         t.set_keyframe(imgs[s], normals[s])
         rs = t.track(frames[s], 3)
-        np.testing.assert_allclose(rb[s]["xi"], rs["xi"], rtol=1e-13, atol=1e-18)
+        np.testing.assert_array_equal(rb[s]["xi"], rs["xi"])
         np.testing.assert_array_equal(b.get_state(s), t.get_state())
         t.close()
     print(f"64-sequence batch frame step {b.last_step_ms():.2f} ms", flush=True)
@@ -212,7 +212,7 @@ def test_device_reanchoring_equals_host_reanchoring():
             rs = t.track(s["frames"][f], 4)
             assert rb[i]["flags"] == rs["flags"] and rb[i]["frames_since_keyframe"] == rs["frames_since_keyframe"]
             np.testing.assert_array_equal(rb[i]["inv_depth"], rs["inv_depth"])
-            np.testing.assert_allclose(rb[i]["T_world"], rs["T_world"], rtol=1e-12, atol=1e-15)
+            np.testing.assert_array_equal(rb[i]["T_world"], rs["T_world"])
             if rs["flags"] & pv.KEYFRAME_DUE:
                 n_due += 1
                 t.set_keyframe(s["frames"][f], s["N_s"])

@@ -23,13 +23,19 @@ hipError_t launch_fu_prologue(const Geo& g, const Strengths& s, const Inputs& in
                               int* health, hipStream_t st);
 hipError_t launch_fu_iterate(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* Y,
                              bool final_pass, float* var_ll, float* valid, int* health, hipStream_t st);
-// one fused iteration X -> Y (prologue into tmp, final pass into Y) that also
-// writes, as the per-factor kernels compute them, for X: the marginals (29
-// FP64 planes) followed by the belief they come from (35), the new messages
-// (116) and the belief of the update, unary + new messages (35)
-hipError_t launch_fu_step_tape(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* tmp,
-                               float* Y, double* marg, float* M, double* bel, float* var_ll, float* valid,
-                               int* health, hipStream_t st);
+// the recompute of a checkpoint segment of len iterations from its canonical
+// state X0, with the tape of every iteration k: the marginals (29 FP64 planes)
+// followed by the belief they come from (35) at marg + k * marg_stride, the
+// information of the new messages (88 FP32) at M + k * M_stride and the
+// belief of the update (35 FP64) at bel + k * bel_stride. The canonical states
+// after iterations 1 .. len - 1 go to seg + k * seg_stride; tA and tB are
+// state-sized work buffers (tB receives the last canonical state). One
+// prologue, len - 1 rotated passes (update of k and prologue of k + 1) and a
+// final pass.
+hipError_t launch_fu_segment_tape(const Geo& g, const Strengths& s, const Inputs& in, const float* X0, float* seg,
+                                  long seg_stride, int len, float* tA, float* tB, double* marg, long marg_stride,
+                                  float* M, long M_stride, double* bel, long bel_stride, float* var_ll, float* valid,
+                                  int* health, hipStream_t st);
 hipError_t launch_valid_only(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* valid,
                              hipStream_t st);
 // statistics records of an image: one per 64 x 4 pixel tile

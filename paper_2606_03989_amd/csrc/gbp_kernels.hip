@@ -453,12 +453,14 @@ __device__ __attribute__((always_inline)) inline void prologue_pixel(const Geo& 
 
 // one iteration of one pixel: complete, update, relinearise, then (not
 // FINAL) emit the next partials or (FINAL) write the canonical state and the
-// per-pixel outputs
+// per-pixel outputs. Not FINAL, Yc (when given) also receives the canonical
+// state after the update, and marg_next the marginals of the next emission.
 template <bool FINAL>
 __device__ __attribute__((always_inline)) inline void iterate_pixel(const Geo& g, const Strengths& s, const Inputs& in, const float* __restrict__ X,
                                      float* __restrict__ Y, float* __restrict__ var_ll, float* __restrict__ valid,
                                      int* __restrict__ health, int u, int v, float* __restrict__ Lam_out = nullptr,
-                                     double* __restrict__ bel_out = nullptr) {
+                                     double* __restrict__ bel_out = nullptr, float* __restrict__ Yc = nullptr,
+                                     double* __restrict__ marg_next = nullptr) {
     const long p = pix_of(g, u, v);
     double tau[6], ell, R[9], t[3], L[28], eta[7];
     load_point(X, g, p, tau, ell);
@@ -482,10 +484,14 @@ __device__ __attribute__((always_inline)) inline void iterate_pixel(const Geo& g
         var_ll[p] = (float)var;
         valid[p] = val ? 1.0f : 0.0f;
     } else {
+        if (Yc) {
+            store_point(Yc, g, p, tau, ell);
+            store_messages(Yc, g, p, mid, mn);
+        }
         se3_exp(tau, R, t);
         unary_factors(g, s, in, u, v, tau, R, t, ell, L, eta);
         add_messages(L, eta, mid, mn);
-        emit_partials(g, s, in, u, v, L, eta, mid, mn, Y, ok);
+        emit_partials(g, s, in, u, v, L, eta, mid, mn, Y, ok, marg_next);
     }
     if (!ok) atomicOr(health, 1);
 }
@@ -829,6 +835,21 @@ __global__ __launch_bounds__(256) void k_fu_prologue_tape(Geo g, Strengths s, In
     const int v = blockIdx.y * blockDim.y + threadIdx.y;
     if (u >= g.W || v >= g.H) return;
     prologue_pixel(g, s, in, X, Y, health, u, v, marg);
+}
+
+// the rotated form of the recompute: the update of iteration k from its
+// partial state X (new messages into M, belief into bel, canonical state
+// k + 1 into Yc) and the prologue of iteration k + 1 (partials into Y,
+// marginals and belief into marg_next) in one pass; the same arithmetic as
+// k_fu_final_tape followed by k_fu_prologue_tape on the canonical state
+__global__ __launch_bounds__(256) void k_fu_rot_tape(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
+                                                     float* __restrict__ Y, float* __restrict__ Yc,
+                                                     float* __restrict__ M, double* __restrict__ bel,
+                                                     double* __restrict__ marg_next, int* __restrict__ health) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y * blockDim.y + threadIdx.y;
+    if (u >= g.W || v >= g.H) return;
+    iterate_pixel<false>(g, s, in, X, Y, nullptr, nullptr, health, u, v, M, bel, Yc, marg_next);
 }
 
 __global__ __launch_bounds__(256) void k_fu_final_tape(Geo g, Strengths s, Inputs in, const float* __restrict__ X,
@@ -1264,12 +1285,21 @@ hipError_t launch_fu_iterate(const Geo& g, const Strengths& s, const Inputs& in,
     return hipGetLastError();
 }
 
-hipError_t launch_fu_step_tape(const Geo& g, const Strengths& s, const Inputs& in, const float* X, float* tmp,
-                               float* Y, double* marg, float* M, double* bel, float* var_ll, float* valid,
-                               int* health, hipStream_t st) {
-    hipLaunchKernelGGL(k_fu_prologue_tape, grid2d(g, kBlockFused), kBlockFused, 0, st, g, s, in, X, tmp, marg, health);
-    hipLaunchKernelGGL(k_fu_final_tape, grid2d(g, kBlockFused), kBlockFused, 0, st, g, s, in, tmp, Y, M, bel, var_ll, valid,
-                       health);
+hipError_t launch_fu_segment_tape(const Geo& g, const Strengths& s, const Inputs& in, const float* X0, float* seg,
+                                  long seg_stride, int len, float* tA, float* tB, double* marg, long marg_stride,
+                                  float* M, long M_stride, double* bel, long bel_stride, float* var_ll, float* valid,
+                                  int* health, hipStream_t st) {
+    if (len < 1) return hipSuccess;
+    const dim3 grid = grid2d(g, kBlockFused);
+    hipLaunchKernelGGL(k_fu_prologue_tape, grid, kBlockFused, 0, st, g, s, in, X0, tA, marg, health);
+    float* t[2] = {tA, tB};
+    for (int k = 0; k + 1 < len; ++k)
+        hipLaunchKernelGGL(k_fu_rot_tape, grid, kBlockFused, 0, st, g, s, in, t[k & 1], t[(k + 1) & 1],
+                           seg + seg_stride * (k + 1), M + M_stride * k, bel + bel_stride * k,
+                           marg + marg_stride * (k + 1), health);
+    const int k = len - 1;
+    hipLaunchKernelGGL(k_fu_final_tape, grid, kBlockFused, 0, st, g, s, in, t[k & 1], t[(k + 1) & 1],
+                       M + M_stride * k, bel + bel_stride * k, var_ll, valid, health);
     return hipGetLastError();
 }
 

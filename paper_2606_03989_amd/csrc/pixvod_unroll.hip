@@ -433,17 +433,15 @@ int pixvod_unroll_backward(pixvod_unroll* u, const double* xi_bar, const float* 
             UHIP(launch_frame_prep(g, u->frames + N * f, u->W, const_cast<float*>(I.It), const_cast<float*>(I.Gx),
                                    const_cast<float*>(I.Gy), u->side));
         // states of the segment: seg[0] = checkpoint, seg[i] after i
-        // iterations; each recompute step also keeps the marginals and the
-        // new messages of its source state (the last step's result is not
-        // needed and goes to a work buffer)
+        // iterations; the recompute also keeps, per iteration, the marginals
+        // and the new messages of its source state (one prologue, then one
+        // rotated pass per iteration; the last state is not needed and goes
+        // to a work buffer)
         const int len = seg_len(u, sg);
         UHIP(hipMemcpyAsync(B.seg, ckpt(u, f, sg), S * sizeof(float), hipMemcpyDeviceToDevice, u->side));
-        for (int k = 0; k < len; ++k) {
-            float* dst = (k + 1 < len) ? B.seg + S * (k + 1) : B.sink;
-            UHIP(launch_fu_step_tape(g, s, I, B.seg + S * k, B.tmp, dst, B.marg + pl * MARG_PLANES * k,
-                                     B.M + pl * LAM_PLANES * k, B.bel + pl * BEL_PLANES * k, u->var_ll, u->valid,
-                                     u->health, u->side));
-        }
+        UHIP(launch_fu_segment_tape(g, s, I, B.seg, B.seg, (long)S, len, B.tmp, B.sink, B.marg,
+                                    (long)(pl * MARG_PLANES), B.M, (long)(pl * LAM_PLANES), B.bel,
+                                    (long)(pl * BEL_PLANES), u->var_ll, u->valid, u->health, u->side));
         UHIP(hipEventRecord(evC[i], u->side));
         return PIXVOD_OK;
     };

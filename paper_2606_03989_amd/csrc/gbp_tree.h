@@ -31,7 +31,10 @@ constexpr int TN_TAU = 0;       // 6
 constexpr int TN_UP = 6;        // 27: message of the parent edge / partial towards the parent
 constexpr int TN_CH = 33;       // 4 x 27: messages of the child edges / partials towards the children
 constexpr int TN_PLANES = 141;
-constexpr int kTreeThreads = 256;
+// lanes per node workgroup: one wave, so that at one wave per SIMD (the node
+// update's register use) each SIMD takes the next workgroup as soon as its
+// own wave ends, and a level is padded to a multiple of 64 nodes only
+constexpr int kTreeThreads = 64;
 
 struct TreeGeo {
     int L;                              // node levels above the pixels

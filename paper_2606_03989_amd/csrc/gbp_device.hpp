@@ -481,6 +481,11 @@ __device__ inline PhotoPre photometric_begin(const Geo& g, const Inputs& in, int
     return p;
 }
 
+// SEL: formed without branches (an invalid warp's pieces are computed from
+// its clamped samples and replaced by zeros, the Huber weight chosen by a
+// select), which lets the caller's independent work be scheduled under the
+// sample loads; the values are those of the branchy form.
+template <bool SEL = false>
 __device__ inline Photo photometric_end(const PhotoPre& p, const Geo& g, const Strengths& s, const double R[9],
                                         const double t[3], const PixelInputs& pin) {
     Photo f;
@@ -489,7 +494,7 @@ __device__ inline Photo photometric_end(const PhotoPre& p, const Geo& g, const S
     f.r = 0.0;
 #pragma unroll
     for (int a = 0; a < 7; ++a) f.J[a] = 0.0;
-    if (!p.valid) return f;
+    if (!SEL && !p.valid) return f;
     f.valid = true;
     const double fx = p.fx, fy = p.fy, iz = p.iz, rho = p.rho, q0 = p.q0, q1 = p.q1;
     const double It = (1.0 - fy) * ((1.0 - fx) * p.s[0] + fx * p.s[1]) + fy * ((1.0 - fx) * p.s[2] + fx * p.s[3]);
@@ -514,22 +519,36 @@ __device__ inline Photo photometric_end(const PhotoPre& p, const Geo& g, const S
     const double lamD = isig * isig;
     const double M = fabs(f.r) * isig;
     double kappa = 1.0;
-    if (M > s.huber_k) {
+    if constexpr (SEL) {
+        const double iM = rcp_nr(M > s.huber_k ? M : 1.0);
+        kappa = (M > s.huber_k) ? s.huber_k * iM * (2.0 - s.huber_k * iM) : 1.0;
+    } else if (M > s.huber_k) {
         const double iM = rcp_nr(M);
         kappa = s.huber_k * iM * (2.0 - s.huber_k * iM);
     }
     f.w = kappa * lamD;
+    if constexpr (SEL) {
+        const bool ok = p.valid;
+        f.valid = ok;
+#pragma unroll
+        for (int a = 0; a < 7; ++a) f.J[a] = ok ? f.J[a] : 0.0;
+        f.w = ok ? f.w : 0.0;
+        f.r = ok ? f.r : 0.0;
+    }
     return f;
 }
 
+template <bool SEL = false>
 __device__ inline Photo photometric(const Geo& g, const Strengths& s, const Inputs& in, int u, int v,
                                     const double R[9], const double t[3], double ell, const PixelInputs& pin) {
-    return photometric_end(photometric_begin(g, in, u, v, R, t, ell), g, s, R, t, pin);
+    return photometric_end<SEL>(photometric_begin(g, in, u, v, R, t, ell), g, s, R, t, pin);
 }
 
-// L += w J^T J, eta -= w J r for a valid photometric factor
+// L += w J^T J, eta -= w J r for a valid photometric factor (SEL: an invalid
+// factor, zero from photometric_end<true>, adds exact zeros)
+template <bool SEL = false>
 __device__ inline void add_photometric(const Photo& f, double L[28], double eta[7]) {
-    if (!f.valid) return;
+    if (!SEL && !f.valid) return;
 #pragma unroll
     for (int a = 0; a < 7; ++a) {
         const double wJa = f.w * f.J[a];
@@ -614,6 +633,7 @@ __device__ inline void add_prior(const Strengths& s, const double tau[6], const 
 }
 
 // the unary belief (photometric + prior) from a photometric factor's pieces
+template <bool SEL = false>
 __device__ inline void unary_from(const Strengths& s, const Photo& f, const double tau[6], const double R[9],
                                   const double t[3], double ell, const PixelInputs& pin, double L[28],
                                   double eta[7]) {
@@ -621,24 +641,26 @@ __device__ inline void unary_from(const Strengths& s, const Photo& f, const doub
     for (int k = 0; k < 28; ++k) L[k] = 0.0;
 #pragma unroll
     for (int k = 0; k < 7; ++k) eta[k] = 0.0;
-    add_photometric(f, L, eta);
+    add_photometric<SEL>(f, L, eta);
     add_prior(s, tau, R, t, ell, pin, L, eta);
 }
 
 // (L, eta) = photometric + prior factors of pixel (u, v) at tau, ell; returns
 // the valid-warp flag
+template <bool SEL = false>
 __device__ inline bool unary_factors(const Geo& g, const Strengths& s, const Inputs& in, int u, int v,
                                      const double tau[6], const double R[9], const double t[3],
                                      double ell, const PixelInputs& pin, double L[28], double eta[7]) {
-    const Photo f = photometric(g, s, in, u, v, R, t, ell, pin);
-    unary_from(s, f, tau, R, t, ell, pin, L, eta);
+    const Photo f = photometric<SEL>(g, s, in, u, v, R, t, ell, pin);
+    unary_from<SEL>(s, f, tau, R, t, ell, pin, L, eta);
     return f.valid;
 }
 
+template <bool SEL = false>
 __device__ inline bool unary_factors(const Geo& g, const Strengths& s, const Inputs& in, int u, int v,
                                      const double tau[6], const double R[9], const double t[3],
                                      double ell, double L[28], double eta[7]) {
-    return unary_factors(g, s, in, u, v, tau, R, t, ell, load_pixel_inputs(g, s, in, u, v), L, eta);
+    return unary_factors<SEL>(g, s, in, u, v, tau, R, t, ell, load_pixel_inputs(g, s, in, u, v), L, eta);
 }
 
 // ---------------------------------------------------------------------------

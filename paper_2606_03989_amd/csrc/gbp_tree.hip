@@ -248,7 +248,7 @@ __global__ __launch_bounds__(256) void k_tr_pixel_prologue(Geo g, TreeGeo t, Str
     double tau[6], ell, R[9], tt[3], L[28], eta[7];
     load_point(X, g, p, tau, ell);
     se3_exp(tau, R, tt);
-    unary_factors(g, s, in, u, v, tau, R, tt, ell, L, eta);
+    unary_factors<true>(g, s, in, u, v, tau, R, tt, ell, L, eta);
     float mup[27], mn[4][2];
     load_part27(X + (long)TP_UP * g.plane, g.plane, p, mup);
 #pragma unroll
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(256) void k_tr_pixel_iterate(Geo g, TreeGeo t, Stre
     double tau[6], ell, R[9], tt[3], L[28], eta[7];
     load_point(X, g, pi, tau, ell);
     se3_exp(tau, R, tt);
-    const bool val = unary_factors(g, s, in, u, v, tau, R, tt, ell, L, eta);
+    const bool val = unary_factors<true>(g, s, in, u, v, tau, R, tt, ell, L, eta);
 
     // the parent's partial for this child slot, completed at both points
     float mup[27];
@@ -343,7 +343,7 @@ __global__ __launch_bounds__(256) void k_tr_pixel_iterate(Geo g, TreeGeo t, Stre
         valid[pi] = val ? 1.0f : 0.0f;
     } else {
         se3_exp(tau, R, tt);
-        unary_factors(g, s, in, u, v, tau, R, tt, ell, L, eta);
+        unary_factors<true>(g, s, in, u, v, tau, R, tt, ell, L, eta);
         add_identity<7>(mup, L, eta);
 #pragma unroll
         for (int d = 0; d < 4; ++d) {

@@ -267,7 +267,9 @@ int pixvod_profile_read(pixvod_ctx* ctx, int kind, double* total_ms, int64_t* la
  * Every pass of the fused schedule is one launch over a work list of
  * (sequence, tile) items; a frame step (frame preparation, prologue, n_iters
  * passes, per-sequence reductions) is captured once as a HIP graph and
- * replayed. Per-pixel arithmetic is the single-sequence code, so results are
+ * replayed. Per-pixel arithmetic is the single-sequence code and the pose
+ * sums are reduced over the same fixed 64 x 4 pixel tiles in the same order
+ * as in a single context, so results (states, pose means, world poses) are
  * identical to per-sequence contexts and independent of the tile shape.
  * All sequences share one parameter set and the fused schedule (damping 0).
  */

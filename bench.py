@@ -163,7 +163,7 @@ def run_gpu(args):
     log(f"frame step: graph replay {g_ms:.3f} ms, passes launched one by one {u_ms:.3f} ms, "
         f"prologue + passes {passes_ms:.3f} ms: {(u_ms - g_ms) * 1e3:.1f} us per frame removed by the graph")
 
-    # the per-factor schedule on the same frames (row a13 baseline)
+    # the per-factor schedule on the same frames (the schedule comparison's baseline)
     per_factor = None
     if args.per_factor_steps > 0:
         tp = make(pv.SCHED_PER_FACTOR)

@@ -210,7 +210,7 @@ __device__ inline void round_point(double tau[6], double& ell) {
 // ---------------------------------------------------------------------------
 // frame and keyframe preparation
 
-// central differences inside, one-sided at the border (row a1)
+// central differences inside, one-sided at the border
 __device__ __attribute__((always_inline)) inline void frame_prep_pixel(const Geo& g, const float* __restrict__ src, long src_pitch,
                                         float* __restrict__ It, float* __restrict__ Gx, float* __restrict__ Gy,
                                         int u, int v) {
@@ -238,7 +238,7 @@ __global__ void k_frame_prep(Geo g, const float* __restrict__ src, long src_pitc
     frame_prep_pixel(g, src, src_pitch, It, Gx, Gy, u, v);
 }
 
-// keyframe image, normal-integration targets (row a2) and the state reset:
+// keyframe image, normal-integration targets and the state reset:
 // pose linearisation points to identity, messages to zero, log-depth kept
 __device__ __attribute__((always_inline)) inline void keyframe_prep_pixel(
     const Geo& g, const float* __restrict__ img, const float* __restrict__ normals, float* __restrict__ Is,
@@ -863,11 +863,10 @@ __global__ __launch_bounds__(256) void k_fu_final_tape(Geo g, Strengths s, Input
 }
 
 // ---------------------------------------------------------------------------
-// per-frame statistics (rows a10-a12), deterministic two-stage reduction
+// per-frame statistics (pose mean, valid count, health), deterministic two-stage reduction
 
 constexpr int RED_THREADS = 256;
 
-// per block: sum of the six pose planes, valid count, non-finite count
 // the eight sums of a workgroup of RED_THREADS work-items: wavefront
 // butterflies (every lane adds the same two operands, in either order), then
 // the wavefronts' sums in order

@@ -183,20 +183,44 @@ __device__ inline void complete_partials(const Geo& g, const Strengths& s, const
     }
 }
 
-__device__ inline void store_point(float* __restrict__ Y, const Geo& g, long p, const double tau[6], double ell) {
-#pragma unroll
-    for (int k = 0; k < 6; ++k) Y[(P_TAU + k) * g.plane + p] = (float)tau[k];
-    Y[P_ELL * g.plane + p] = (float)ell;
+// one float of state; NT: a non-temporal store (streamed past the caches),
+// for passes whose output is not read again while it could stay cached: the
+// batch's passes over many sequences and a frame's final pass
+template <bool NT = false>
+__device__ inline void put(float* __restrict__ a, float v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, a);
+    else *a = v;
 }
 
+template <bool NT = false>
+__device__ inline void store_point(float* __restrict__ Y, const Geo& g, long p, const double tau[6], double ell) {
+    if constexpr (NT) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) put<true>(&Y[(P_TAU + k) * g.plane + p], (float)tau[k]);
+        put<true>(&Y[P_ELL * g.plane + p], (float)ell);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Y[(P_TAU + k) * g.plane + p] = (float)tau[k];
+        Y[P_ELL * g.plane + p] = (float)ell;
+    }
+}
+
+template <bool NT = false>
 __device__ inline void store_messages(float* __restrict__ Y, const Geo& g, long p, const float mid[4][27],
                                       const float mn[4][2]) {
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
+        if constexpr (NT) {
 #pragma unroll
-        for (int k = 0; k < 27; ++k) Y[(long)(P_MID + d * MID_STRIDE + k) * g.plane + p] = mid[d][k];
-        Y[(long)(P_MN + 2 * d) * g.plane + p] = mn[d][0];
-        Y[(long)(P_MN + 2 * d + 1) * g.plane + p] = mn[d][1];
+            for (int k = 0; k < 27; ++k) put<true>(&Y[(long)(P_MID + d * MID_STRIDE + k) * g.plane + p], mid[d][k]);
+            put<true>(&Y[(long)(P_MN + 2 * d) * g.plane + p], mn[d][0]);
+            put<true>(&Y[(long)(P_MN + 2 * d + 1) * g.plane + p], mn[d][1]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 27; ++k) Y[(long)(P_MID + d * MID_STRIDE + k) * g.plane + p] = mid[d][k];
+            Y[(long)(P_MN + 2 * d) * g.plane + p] = mn[d][0];
+            Y[(long)(P_MN + 2 * d + 1) * g.plane + p] = mn[d][1];
+        }
     }
 }
 
@@ -580,7 +604,7 @@ __device__ inline void prefetch_messages(const Geo& g, const float* __restrict__
 // the wait is explicit, and the memory clobber keeps the LDS reads after it
 __device__ inline void wait_lds_loads() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-template <bool FINAL, bool SH, bool PIPE = false>
+template <bool FINAL, bool SH, bool PIPE = false, bool NT = false>
 __device__ __attribute__((always_inline)) inline void iterate_pixel_pf(
     const Geo& g, const Strengths& s, const Inputs& in, const float* __restrict__ X, float* __restrict__ Y,
     float* __restrict__ var_ll, float* __restrict__ valid, int* __restrict__ health, int u, int v,
@@ -720,9 +744,9 @@ __device__ __attribute__((always_inline)) inline void iterate_pixel_pf(
     double var;
     bool ok = update_and_transport(L, eta, tau, ell, mid, mn, var);
     round_point(tau, ell);
-    store_point(Y, g, p, tau, ell);
+    store_point<NT>(Y, g, p, tau, ell);
     if (FINAL) {
-        store_messages(Y, g, p, mid, mn);
+        store_messages<NT>(Y, g, p, mid, mn);
         var_ll[p] = (float)var;
         valid[p] = val ? 1.0f : 0.0f;
     } else {
@@ -749,16 +773,31 @@ __device__ __attribute__((always_inline)) inline void iterate_pixel_pf(
             for (int k = 0; k < 6; ++k) vv[k] = pm[k] - (double)mid[d][k];
             ok = identity_partial(s.lamR, V, vv, Lp, h) && ok;
             float* dst = Y + (long)(P_MID + slot * MID_STRIDE) * g.plane + pj;
+            if constexpr (NT) {
 #pragma unroll
-            for (int k = 0; k < 6; ++k) dst[k * g.plane] = (float)h[k];
+                for (int k = 0; k < 6; ++k) put<true>(&dst[k * g.plane], (float)h[k]);
 #pragma unroll
-            for (int k = 0; k < 21; ++k) dst[(6 + k) * g.plane] = (float)Lp[k];
+                for (int k = 0; k < 21; ++k) put<true>(&dst[(6 + k) * g.plane], (float)Lp[k]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) dst[k * g.plane] = (float)h[k];
+#pragma unroll
+                for (int k = 0; k < 21; ++k) dst[(6 + k) * g.plane] = (float)Lp[k];
+            }
             float* dn = Y + (long)(P_MN + 2 * slot) * g.plane + pj;
             if (isfinite(ct.c[d]) && s.lamN > 0.0) {
                 double lp, hn;
                 normal_partial(s.lamN, D - (double)mn[d][1], dv - (double)mn[d][0], lp, hn);
-                dn[0] = (float)hn;
-                dn[g.plane] = (float)lp;
+                if constexpr (NT) {
+                    put<true>(&dn[0], (float)hn);
+                    put<true>(&dn[g.plane], (float)lp);
+                } else {
+                    dn[0] = (float)hn;
+                    dn[g.plane] = (float)lp;
+                }
+            } else if constexpr (NT) {
+                put<true>(&dn[0], 0.0f);
+                put<true>(&dn[g.plane], 0.0f);
             } else {
                 dn[0] = 0.0f;
                 dn[g.plane] = 0.0f;
@@ -818,7 +857,7 @@ __global__ __launch_bounds__(256) void k_fu_iterate(Geo g, Strengths s, Inputs i
         it.prior_ell += z;
         const int tz = tid + z;
         __syncthreads();   // the previous tile's readers of the shared table are done
-        iterate_pixel_pf<FINAL, true, true>(gt, s, it, X + z, Y + z, var_ll + z, valid + z, health, u + z, v + z,
+        iterate_pixel_pf<FINAL, true, true, FINAL>(gt, s, it, X + z, Y + z, var_ll + z, valid + z, health, u + z, v + z,
                                             u < g.W && v < g.H, sh, u0, v0, tz, mbuf, next < ntiles,
                                             (next % tiles_x) * 64, (next / tiles_x) * 4);
     }
@@ -1032,7 +1071,7 @@ __global__ __launch_bounds__(256) void k_batch_iterate(const SeqDesc* __restrict
     if (!batch_pixel(seqs, work, d, u, v, item)) return;
     const float* X = parity ? d->X1 : d->X0;
     float* Y = parity ? d->X0 : d->X1;
-    iterate_pixel_pf<FINAL, false>(d->g, s, d->in, X, Y, d->var_ll, d->valid, health, u, v);
+    iterate_pixel_pf<FINAL, false, false, true>(d->g, s, d->in, X, Y, d->var_ll, d->valid, health, u, v);
 }
 
 // per sequence (blockIdx.y) and 64 x 4 tile of its image (blockIdx.x): the
@@ -1127,7 +1166,7 @@ __global__ __launch_bounds__(256) void k_batch_persistent(const SeqDesc* __restr
             if (u < d->g.W && v < d->g.H) {
                 const float* X = par ? d->X1 : d->X0;
                 float* Y = par ? d->X0 : d->X1;
-                iterate_pixel_pf<false, false>(d->g, s, d->in, X, Y, d->var_ll, d->valid, health, u, v);
+                iterate_pixel_pf<false, false, false, true>(d->g, s, d->in, X, Y, d->var_ll, d->valid, health, u, v);
             }
         }
         if (pass + 1 < n_passes) grid.sync();

@@ -63,17 +63,18 @@ __device__ inline void emit_partials(const Geo& g, const Strengths& s, const Inp
     const long pi = pix_of(g, u, v);
     if (marg_out) {
         // the marginals in the per-factor layout (k_pf_linearise): P 21, p 6,
-        // D, dv; then the belief they come from: L 28, eta 7
+        // D, dv; then the belief they come from: L 28, eta 7 (the reverse
+        // sweep's tape, written non-temporally)
 #pragma unroll
-        for (int k = 0; k < 21; ++k) marg_out[(long)k * g.plane + pi] = P[k];
+        for (int k = 0; k < 21; ++k) __builtin_nontemporal_store(P[k], &marg_out[(long)k * g.plane + pi]);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) marg_out[(long)(21 + k) * g.plane + pi] = p[k];
-        marg_out[27L * g.plane + pi] = D;
-        marg_out[28L * g.plane + pi] = dv;
+        for (int k = 0; k < 6; ++k) __builtin_nontemporal_store(p[k], &marg_out[(long)(21 + k) * g.plane + pi]);
+        __builtin_nontemporal_store(D, &marg_out[27L * g.plane + pi]);
+        __builtin_nontemporal_store(dv, &marg_out[28L * g.plane + pi]);
 #pragma unroll
-        for (int k = 0; k < 28; ++k) marg_out[(long)(29 + k) * g.plane + pi] = L[k];
+        for (int k = 0; k < 28; ++k) __builtin_nontemporal_store(L[k], &marg_out[(long)(29 + k) * g.plane + pi]);
 #pragma unroll
-        for (int k = 0; k < 7; ++k) marg_out[(long)(57 + k) * g.plane + pi] = eta[k];
+        for (int k = 0; k < 7; ++k) __builtin_nontemporal_store(eta[k], &marg_out[(long)(57 + k) * g.plane + pi]);
     }
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
@@ -493,11 +494,13 @@ __device__ __attribute__((always_inline)) inline void iterate_pixel(const Geo& g
     float mid[4][27], mn[4][2];
     complete_partials(g, s, in, X, u, v, R, t, ell, L, eta, mid, mn, Lam_out);
     if (bel_out) {
-        // the belief of the update (unary + new messages): L 28, eta 7
+        // the belief of the update (unary + new messages): L 28, eta 7; the
+        // FP64 tape is written non-temporally (read back only by the reverse
+        // sweep, after the segment's recompute)
 #pragma unroll
-        for (int k = 0; k < 28; ++k) bel_out[(long)k * g.plane + p] = L[k];
+        for (int k = 0; k < 28; ++k) __builtin_nontemporal_store(L[k], &bel_out[(long)k * g.plane + p]);
 #pragma unroll
-        for (int k = 0; k < 7; ++k) bel_out[(long)(28 + k) * g.plane + p] = eta[k];
+        for (int k = 0; k < 7; ++k) __builtin_nontemporal_store(eta[k], &bel_out[(long)(28 + k) * g.plane + p]);
     }
     double var;
     bool ok = update_and_transport(L, eta, tau, ell, mid, mn, var);

@@ -146,7 +146,7 @@ __device__ inline void complete_partials(const Geo& g, const Strengths& s, const
             mn[d][0] = mn[d][1] = 0.0f;
             if (Lam_out)
 #pragma unroll
-                for (int k = 0; k < LAM_STRIDE; ++k) Lam_out[(long)(d * LAM_STRIDE + k) * g.plane + pi] = 0.0f;
+                for (int k = 0; k < LAM_STRIDE; ++k) __builtin_nontemporal_store(0.0f, &Lam_out[(long)(d * LAM_STRIDE + k) * g.plane + pi]);
             continue;
         }
         const long pj = pix_of(g, nu, nv);
@@ -176,10 +176,12 @@ __device__ inline void complete_partials(const Geo& g, const Strengths& s, const
         }
         accumulate_message(L, eta, e6, part + 6, ne, nl, mid[d], mn[d]);
         if (Lam_out) {
+            // the reverse sweep's tape of the new messages' information, written
+            // non-temporally like the FP64 tape
             float* o = Lam_out + (long)(d * LAM_STRIDE) * g.plane + pi;
 #pragma unroll
-            for (int k = 0; k < 21; ++k) o[k * g.plane] = part[6 + k];
-            o[21 * g.plane] = nl;
+            for (int k = 0; k < 21; ++k) __builtin_nontemporal_store(part[6 + k], &o[k * g.plane]);
+            __builtin_nontemporal_store(nl, &o[21 * g.plane]);
         }
     }
 }
